@@ -1,0 +1,54 @@
+"""Pins of the input generators: the Lane-Emden integrator against its three
+closed-form solutions, and the structure of the seeded workloads."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1507_08549_amd import inputs
+
+
+@pytest.mark.parametrize("n,exact,xi1", [
+    (0, lambda x: 1 - x * x / 6, math.sqrt(6.0)),
+    (1, lambda x: np.sinc(x / math.pi), math.pi),
+    (5, lambda x: (1 + x * x / 3) ** -0.5, math.inf),
+])
+def test_lane_emden_closed_forms(n, exact, xi1):
+    xi, th, dth, z = inputs.lane_emden(n, 1e-3)
+    sel = xi < min(xi1, 10.0) - 1e-2
+    assert np.abs(th[sel] - exact(xi[sel])).max() < 1e-9
+    if math.isfinite(xi1):
+        assert abs(z - xi1) < 1e-6
+    else:
+        assert math.isinf(z)
+
+
+def test_lane_emden_n3_derivative_consistent():
+    xi, th, dth, z = inputs.lane_emden(3, 1e-3)
+    mid = slice(1000, -1000)
+    num = np.gradient(th, xi)[mid]
+    assert np.abs(num - dth[mid]).max() < 1e-5
+    assert 6.89 < z < 6.90
+
+
+def test_polytrope_is_hydrostatic_to_discretisation_error():
+    """dp/dR = rho g_R inside the star (the generator's p and g are consistent)."""
+    prm, U, g = inputs.polytrope(n=128, noise=0.0)
+    rho, u, v, p = inputs.primitive_from_state(U, prm["gamma"])
+    dx = (prm["xhi"] - prm["xlo"]) / prm["nx"]
+    j = 2  # a row near the equatorial plane: d/dr along it
+    dpdr = np.gradient(p[j], dx)
+    inside = rho[j] > 1e-3
+    rel = np.abs(dpdr - rho[j] * g[0, j])[inside] / np.abs(rho[j] * g[0, j])[inside].max()
+    assert rel[5:-5].max() < 2e-2
+
+
+def test_workload_shapes_and_seeds():
+    prm, U = inputs.kelvin_helmholtz(64, seed=2)
+    assert U.shape == (4, 64, 64) and prm["bc"] == [0, 0, 0, 0]
+    _, U2 = inputs.kelvin_helmholtz(64, seed=2)
+    assert np.array_equal(U, U2)
+    prm, U = inputs.rayleigh_taylor(32, 128)
+    assert U.shape == (4, 128, 32) and prm["gy"] == -0.1
+    prm, U = inputs.sod(400)
+    assert U.shape == (4, 1, 400)

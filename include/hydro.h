@@ -1,0 +1,168 @@
+/*
+ * hydro.h -- C ABI of the MI355X (gfx950) WENO5 Euler solver.
+ *
+ * The library advances the two-dimensional Euler equations in conservative
+ * form with source terms (Eq. euler2D of Sect. 2.1: Cartesian (x, y) or
+ * cylindrical (r, z) with the geometric terms -(1/r)(...), a fixed gravity
+ * field g = -grad Phi, no heat source), using the discretisation Sect. 2.1
+ * describes: finite-difference fifth-order WENO (Jiang & Shu 1996) applied to
+ * both halves of a global Lax-Friedrichs flux splitting, an ideal-gas EOS
+ * p = (gamma - 1) rho eps (Sect. 5.1), third-order SSP Runge-Kutta time
+ * stepping and the CFL step of Sect. 5.3.
+ *
+ * Conventions for every entry point
+ *  - Return value: HYDRO_OK (0) or a negative HYDRO_E_* code.  No call
+ *    throws, aborts or prints.  hydro_strerror() names a code.
+ *  - State arrays are caller-owned DEVICE buffers of 4 * ny * nx doubles,
+ *    component-major [4][ny][nx] (row j = y index, i = x index, x fastest),
+ *    components (rho, m_x, m_y, E): density, momentum density (m = rho v;
+ *    m_r, m_z in cylindrical geometry) and total energy density
+ *    E = rho eps + rho |v|^2 / 2 (the paper's tau).  Values are point values
+ *    at cell centres x_i = xlo + (i + 1/2) dx, y_j = ylo + (j + 1/2) dy.
+ *  - A context owns its scratch memory (stage states, reduction slots, an
+ *    error flag) from hydro_create to hydro_destroy and is bound to one HIP
+ *    stream.  Calls enqueue work on that stream and return without waiting
+ *    unless stated ("synchronises").  A context is not thread-safe; several
+ *    contexts may share a device.
+ *  - Device buffers passed in must stay valid until the enqueued work has
+ *    finished.  Pointers are checked for NULL only.
+ *  - HYDRO_E_UNPHYSICAL is sticky: a stage that produces rho <= 0 or p <= 0
+ *    (after the optional atmosphere floors) sets a device flag; the next
+ *    synchronising call returns the code and hydro_check() clears it.
+ */
+#ifndef HYDRO_H
+#define HYDRO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  HYDRO_OK = 0,
+  HYDRO_E_INVALID = -1,    /* bad parameters, sizes or NULL pointers */
+  HYDRO_E_NOMEM = -2,      /* device allocation failed */
+  HYDRO_E_DEVICE = -3,     /* a HIP runtime call failed */
+  HYDRO_E_UNPHYSICAL = -4, /* rho <= 0 or p <= 0 (or non-finite) was produced */
+  HYDRO_E_STATE = -5       /* call not valid in the context's current state */
+};
+
+enum { HYDRO_PERIODIC = 0, HYDRO_TRANSMISSIVE = 1, HYDRO_REFLECTING = 2 };
+enum { HYDRO_CARTESIAN = 0, HYDRO_CYLINDRICAL = 1 };
+enum { HYDRO_FP64 = 0, HYDRO_FP32_BULK = 1 };
+
+/* Problem description (Sect. 2.1, Eq. euler2D).
+ *  nx, ny      interior cells; nx >= 3; ny == 1 is the 1D limit (no y sweep,
+ *              as in the one-dimensional tests of Sect. 5.1), else ny >= 3.
+ *  domain      [xlo, xhi] x [ylo, yhi]; cylindrical: x = r >= 0, y = z.
+ *  geometry    HYDRO_CARTESIAN or HYDRO_CYLINDRICAL (adds -(1/r)(m_r, m_r v_r,
+ *              m_z v_r, (E + p) v_r) at r_i = xlo + (i + 1/2) dx).
+ *  bc[4]       x-low, x-high, y-low, y-high: periodic (both sides of an axis
+ *              or neither), transmissive (zero gradient: the paper's "free"
+ *              boundary) or reflecting (mirror, normal momentum negated: the
+ *              r = 0 axis and z = 0 plane).  Three ghost layers.
+ *  gamma       ideal-gas ratio of specific heats (> 1).
+ *  cfl         Courant number c_cfl of the CFL step (Sect. 5.3).
+ *  weno_eps    epsilon of the WENO weights (1e-6 is the usual choice).
+ *  precision   HYDRO_FP64: every operation in FP64.  HYDRO_FP32_BULK: primitive
+ *              variables, split fluxes, reconstructions and the divergence in
+ *              FP32; stage accumulation, the CFL / LF-speed reductions and the
+ *              conservation sums stay FP64; states stay FP64 in memory.
+ *  gx, gy      uniform gravity, used when no gravity field is given.
+ *  rho_floor   > 0 enables the atmosphere floors after every stage (Sect. 5.3:
+ *  p_floor     minimum density): a cell with rho < rho_floor becomes
+ *              (rho_floor, 0, 0, p_floor / (gamma - 1)); then a cell with
+ *              p < p_floor gets E = p_floor / (gamma - 1) + m.v / 2 (rho and m
+ *              kept).  p_floor must then be > 0.  rho_floor <= 0 disables both. */
+typedef struct {
+  int32_t nx, ny;
+  double xlo, xhi, ylo, yhi;
+  int32_t geometry;
+  int32_t bc[4];
+  double gamma, cfl, weno_eps;
+  int32_t precision;
+  double gx, gy;
+  double rho_floor, p_floor;
+} hydro_params;
+
+/* Global Lax-Friedrichs speeds of the three Runge-Kutta stages (Sect. 2.1:
+ * alpha_x = max over interior cells of |v_x| + c, alpha_y = max |v_y| + c,
+ * each taken from the stage's input state).  Recorded by the forward step and
+ * replayed ("frozen") by the adjoint. */
+typedef struct {
+  double ax[3], ay[3];
+} hydro_alpha;
+
+typedef struct hydro_ctx hydro_ctx;
+
+/* Create a context on the current HIP device.
+ *  params   copied.
+ *  gravity  NULL (uniform params->gx, gy) or a device field [2][ny][nx] of
+ *           (g_x, g_y) per cell; borrowed, must outlive the context.
+ *  stream   a hipStream_t, or NULL for the null stream.
+ *  out      receives the context.
+ * Allocates 6 state-sized scratch buffers.  Errors: INVALID, NOMEM, DEVICE. */
+int hydro_create(const hydro_params* params, const double* gravity, void* stream,
+                 hydro_ctx** out);
+
+/* Free the context's scratch (waits for its stream).  NULL is accepted. */
+int hydro_destroy(hydro_ctx* ctx);
+
+/* CFL time step of state U (Sect. 5.3): dt = cfl * min(dx, dy) / max over
+ * interior cells of (c + |v_x| + |v_y|) (dx alone when ny == 1).
+ * Synchronises; *dt_host receives the value.  UNPHYSICAL if U has rho <= 0
+ * or p <= 0 somewhere. */
+int hydro_cfl(hydro_ctx* ctx, const double* U, double* dt_host);
+
+/* One SSP-RK3 step of size dt, in place: U <- U^{n+1}.
+ *  alpha_in   NULL: each stage computes its LF speeds from its input (the
+ *             method); else the given speeds are used (replay of a recorded
+ *             schedule, as the adjoint requires).
+ *  alpha_out  NULL, or receives the speeds used (then the call synchronises).
+ * Asynchronous otherwise. */
+int hydro_step(hydro_ctx* ctx, double* U, double dt, const hydro_alpha* alpha_in,
+               hydro_alpha* alpha_out);
+
+/* Up to nsteps steps with the CFL time step computed on the device (no host
+ * round trip between steps), each clamped so that t never passes t_end
+ * (t_end <= 0: no clamp, exactly nsteps steps).
+ *  t_io       in: start time; out: time reached.
+ *  dt_rec     NULL or device [nsteps] doubles: the dt of each step taken.
+ *  alpha_rec  NULL or device [nsteps][6] doubles (ax[0..2], ay[0..2] of each
+ *             step, the layout of hydro_alpha).
+ * Synchronises at the end.  Returns the number of steps taken (>= 0) or an
+ * error code. */
+int hydro_run(hydro_ctx* ctx, double* U, int32_t nsteps, double t_end, double* t_io,
+              double* dt_rec, double* alpha_rec);
+
+/* The spatial operator alone: L = S(V) - (dF/dx + dG/dy) for given LF speeds
+ * (the right-hand side each Runge-Kutta stage integrates).  L: device
+ * [4][ny][nx], overwritten.  Asynchronous. */
+int hydro_rhs(hydro_ctx* ctx, const double* V, double ax, double ay, double* L);
+
+/* Discrete adjoint of one step: lam_prev = (dU^{n+1}/dU^n)^T lam_next for the
+ * step hydro_step(U_n, dt, alpha) performs with the given (recorded) LF speeds
+ * held fixed.  Recomputes the two intermediate stage states from U_n.
+ * U_n, lam_next: device [4][ny][nx], read only; lam_prev: device
+ * [4][ny][nx], overwritten (may not alias the others).  The atmosphere
+ * floors must be disabled (INVALID otherwise).  Asynchronous. */
+int hydro_step_vjp(hydro_ctx* ctx, const double* U_n, double dt, const hydro_alpha* alpha,
+                   const double* lam_next, double* lam_prev);
+
+/* Totals of rho, m_x, m_y, E times the cell volume (dx dy; 2 pi r_i dx dy in
+ * cylindrical geometry), with compensated (Neumaier) summation in a fixed
+ * order.  Synchronises; out_host[4] receives them. */
+int hydro_sums(hydro_ctx* ctx, const double* U, double out_host[4]);
+
+/* Synchronise and return (then clear) the sticky UNPHYSICAL flag. */
+int hydro_check(hydro_ctx* ctx);
+
+/* Static string naming an error code. */
+const char* hydro_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HYDRO_H */

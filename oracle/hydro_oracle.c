@@ -63,7 +63,7 @@ typedef struct {
   int32_t bc[4];              /* x-low, x-high, y-low, y-high */
   double gamma, cfl, eps;
   double gx, gy;              /* uniform gravity (used when no field is given) */
-  double rho_floor, p_floor;  /* floor reset after each stage when rho_floor > 0 */
+  double rho_floor, p_floor;  /* atmosphere floors applied after each stage when rho_floor > 0 */
 } orc_params;
 
 /* ---------------------------------------------------------------- helpers */
@@ -424,14 +424,21 @@ int orc_step(const orc_params *p, const double *gravity, double *U, double dt,
     if (rc) { status = rc; break; }
     for (size_t q = 0; q < n4; ++q) W[q] = fma(cb[s], fma(dt, L[q], V[q] - U[q]), U[q]);
     if (p->rho_floor > 0.0) {
-      /* atmosphere reset (Sect. 5.3): rho < floor -> floor density at rest */
-      for (size_t k = 0; k < n; ++k)
+      /* atmosphere (Sect. 5.3 enforces a minimum density, the atmosphere's):
+       * rho < rho_floor -> the atmosphere state at rest; then, for the ideal
+       * gas, p < p_floor -> internal energy raised to the atmosphere's
+       * pressure with rho and m kept. */
+      for (size_t k = 0; k < n; ++k) {
         if (W[k] < p->rho_floor) {
           W[k] = p->rho_floor;
           W[n + k] = 0.0;
           W[2 * n + k] = 0.0;
           W[3 * n + k] = p->p_floor / (p->gamma - 1.0);
         }
+        prim_t w = cons_to_prim(W[k], W[n + k], W[2 * n + k], W[3 * n + k], p->gamma);
+        if (w.p < p->p_floor)
+          W[3 * n + k] = p->p_floor / (p->gamma - 1.0) + 0.5 * (W[n + k] * w.u + W[2 * n + k] * w.v);
+      }
     }
     for (size_t k = 0; k < n; ++k) {
       prim_t w = cons_to_prim(W[k], W[n + k], W[2 * n + k], W[3 * n + k], p->gamma);

@@ -1,0 +1,376 @@
+// hydro_api.cpp -- the C ABI declared in include/hydro.h: context management,
+// parameter checks, and the launch sequences of the forward step, the
+// multi-step run with a device-side CFL step, the spatial operator, the
+// reductions and the discrete adjoint.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "hydro.h"
+#include "hydro_internal.hpp"
+#include "vjp.hpp"
+
+struct hydro_ctx {
+  hydro_params p;
+  hy::Geom g;
+  hipStream_t stream;
+  int device;
+  size_t n;              // cells
+  double* U1;            // stage states
+  double* U2;
+  double* X[4];          // adjoint scratch: recomputed stage states, stage adjoints
+  hy::Ctl* ctl;          // device control block
+  double* rec;           // device: alpha record of hydro_step ([6])
+  double* partial;       // device: per-block partial sums
+  double* sum_out;       // device: [4]
+  double* ghost;         // device: adjoint of ghost cells ([2][3][max(nx, ny)][4] per axis)
+  int nsum;
+  hy::Ctl* h_ctl;        // pinned host staging
+  double* h_buf;         // pinned host staging ([8])
+};
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) { ok = false; return; }
+    if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+#define HY_CHECK(call)                                  \
+  do {                                                  \
+    if ((call) != hipSuccess) return HYDRO_E_DEVICE;    \
+  } while (0)
+
+int check_params(const hydro_params* p) {
+  if (!p) return HYDRO_E_INVALID;
+  if (p->nx < 3 || p->ny < 1 || (p->ny > 1 && p->ny < 3)) return HYDRO_E_INVALID;
+  if ((long long)p->nx * (long long)p->ny > (1LL << 31) - 1) return HYDRO_E_INVALID;
+  if (!(p->xhi > p->xlo) || !(p->yhi > p->ylo)) return HYDRO_E_INVALID;
+  if (!(p->gamma > 1.0) || !(p->weno_eps > 0.0) || !(p->cfl > 0.0)) return HYDRO_E_INVALID;
+  if (!std::isfinite(p->gx) || !std::isfinite(p->gy)) return HYDRO_E_INVALID;
+  for (int k = 0; k < 4; ++k)
+    if (p->bc[k] < 0 || p->bc[k] > 2) return HYDRO_E_INVALID;
+  if ((p->bc[0] == HYDRO_PERIODIC) != (p->bc[1] == HYDRO_PERIODIC)) return HYDRO_E_INVALID;
+  if ((p->bc[2] == HYDRO_PERIODIC) != (p->bc[3] == HYDRO_PERIODIC)) return HYDRO_E_INVALID;
+  if (p->geometry != HYDRO_CARTESIAN && p->geometry != HYDRO_CYLINDRICAL) return HYDRO_E_INVALID;
+  if (p->geometry == HYDRO_CYLINDRICAL && p->xlo < 0.0) return HYDRO_E_INVALID;
+  if (p->precision != HYDRO_FP64 && p->precision != HYDRO_FP32_BULK) return HYDRO_E_INVALID;
+  if (p->rho_floor > 0.0 && !(p->p_floor > 0.0)) return HYDRO_E_INVALID;
+  return HYDRO_OK;
+}
+
+// Derived constants, each formed with the same operations as a direct
+// evaluation (so the kernels' arithmetic does not depend on where they were
+// formed).
+hy::Geom make_geom(const hydro_params* p, const double* gravity) {
+  hy::Geom g{};
+  g.nx = p->nx;
+  g.ny = p->ny;
+  g.has_y = p->ny > 1;
+  for (int k = 0; k < 4; ++k) g.bc[k] = p->bc[k];
+  g.cyl = p->geometry == HYDRO_CYLINDRICAL;
+  g.dx = (p->xhi - p->xlo) / (double)p->nx;
+  g.dy = (p->yhi - p->ylo) / (double)p->ny;
+  g.idx = 1.0 / g.dx;
+  g.idy = 1.0 / g.dy;
+  g.xlo = p->xlo;
+  g.gamma = p->gamma;
+  g.gm1 = p->gamma - 1.0;
+  g.eps = p->weno_eps;
+  g.gx = p->gx;
+  g.gy = p->gy;
+  g.grav = gravity;
+  g.floor_on = p->rho_floor > 0.0;
+  g.rho_floor = p->rho_floor;
+  g.p_floor = p->p_floor;
+  g.e_floor = p->p_floor / (p->gamma - 1.0);
+  double dmin = g.dx;
+  if (g.has_y && g.dy < dmin) dmin = g.dy;
+  g.cfl_dmin = p->cfl * dmin;
+  return g;
+}
+
+__global__ void set_ctl_kernel(hy::Ctl* ctl, double t) {
+  if (threadIdx.x == 0) {
+    ctl->t = t;
+    ctl->dt = 0.0;
+    ctl->active = 1;
+    ctl->steps = 0;
+  }
+}
+
+hipError_t launch_stage(const hydro_ctx* c, const hy::StageArgs& a) {
+  return c->p.precision == HYDRO_FP64 ? hy::launch_stage_fp64(a, c->stream)
+                                      : hy::launch_stage_fp32(a, c->stream);
+}
+
+const double kStageWeight[3] = {1.0, 0.25, 2.0 / 3.0};
+
+hy::StageArgs stage_args(const hydro_ctx* c, double* U, int s) {
+  hy::StageArgs a{};
+  a.g = c->g;
+  a.U0 = U;
+  a.V = s == 0 ? U : (s == 1 ? c->U1 : c->U2);
+  a.W = s == 0 ? c->U1 : (s == 1 ? c->U2 : U);
+  a.b = kStageWeight[s];
+  a.stage = s;
+  a.ctl = c->ctl;
+  return a;
+}
+
+int read_flag(hydro_ctx* c, bool clear) {
+  HY_CHECK(hipMemcpyAsync(c->h_ctl, c->ctl, sizeof(hy::Ctl), hipMemcpyDeviceToHost, c->stream));
+  HY_CHECK(hipStreamSynchronize(c->stream));
+  const int f = c->h_ctl->flag;
+  if (f && clear) {
+    HY_CHECK(hipMemsetAsync(&c->ctl->flag, 0, sizeof(int), c->stream));
+    HY_CHECK(hipStreamSynchronize(c->stream));
+  }
+  return f ? HYDRO_E_UNPHYSICAL : HYDRO_OK;
+}
+
+void free_ctx(hydro_ctx* c) {
+  if (!c) return;
+  (void)hipFree(c->U1);
+  (void)hipFree(c->U2);
+  for (double* x : c->X) (void)hipFree(x);
+  (void)hipFree(c->ctl);
+  (void)hipFree(c->rec);
+  (void)hipFree(c->partial);
+  (void)hipFree(c->sum_out);
+  (void)hipFree(c->ghost);
+  (void)hipHostFree(c->h_ctl);
+  (void)hipHostFree(c->h_buf);
+  delete c;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hydro_create(const hydro_params* params, const double* gravity, void* stream, hydro_ctx** out) {
+  if (!out) return HYDRO_E_INVALID;
+  *out = nullptr;
+  int rc = check_params(params);
+  if (rc) return rc;
+  hydro_ctx* c = new (std::nothrow) hydro_ctx();
+  if (!c) return HYDRO_E_NOMEM;
+  c->p = *params;
+  c->g = make_geom(params, gravity);
+  c->stream = (hipStream_t)stream;
+  if (hipGetDevice(&c->device) != hipSuccess) { delete c; return HYDRO_E_DEVICE; }
+  c->n = (size_t)params->nx * (size_t)params->ny;
+  const size_t bytes = 4 * c->n * sizeof(double);
+  c->nsum = hy::sums_blocks(c->g);
+  bool ok = hipMalloc(&c->U1, bytes) == hipSuccess && hipMalloc(&c->U2, bytes) == hipSuccess;
+  for (int k = 0; k < 4 && ok; ++k) ok = hipMalloc(&c->X[k], bytes) == hipSuccess;
+  ok = ok && hipMalloc(&c->ctl, sizeof(hy::Ctl)) == hipSuccess;
+  ok = ok && hipMalloc(&c->rec, 8 * sizeof(double)) == hipSuccess;
+  ok = ok && hipMalloc(&c->partial, (size_t)c->nsum * 8 * sizeof(double)) == hipSuccess;
+  ok = ok && hipMalloc(&c->sum_out, 4 * sizeof(double)) == hipSuccess;
+  const size_t nmax = (size_t)(params->nx > params->ny ? params->nx : params->ny);
+  ok = ok && hipMalloc(&c->ghost, 2 * 2 * 3 * nmax * 4 * sizeof(double)) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&c->h_ctl, sizeof(hy::Ctl), hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&c->h_buf, 8 * sizeof(double), hipHostMallocDefault) == hipSuccess;
+  if (!ok) {
+    free_ctx(c);
+    (void)hipGetLastError();
+    return HYDRO_E_NOMEM;
+  }
+  if (hipMemsetAsync(c->ctl, 0, sizeof(hy::Ctl), c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
+    free_ctx(c);
+    return HYDRO_E_DEVICE;
+  }
+  *out = c;
+  return HYDRO_OK;
+}
+
+int hydro_destroy(hydro_ctx* c) {
+  if (!c) return HYDRO_OK;
+  DeviceGuard dg(c->device);
+  int rc = (hipStreamSynchronize(c->stream) == hipSuccess) ? HYDRO_OK : HYDRO_E_DEVICE;
+  free_ctx(c);
+  return rc;
+}
+
+int hydro_cfl(hydro_ctx* c, const double* U, double* dt_host) {
+  if (!c || !U || !dt_host) return HYDRO_E_INVALID;
+  DeviceGuard dg(c->device);
+  if (!dg.ok) return HYDRO_E_DEVICE;
+  HY_CHECK(hy::launch_clear_slots(c->ctl, c->stream));
+  HY_CHECK(hy::launch_alpha_reduce(c->g, U, c->ctl, 0, c->stream));
+  int rc = read_flag(c, false);
+  if (rc) return rc;
+  const double smax = *reinterpret_cast<const double*>(&c->h_ctl->slot[0][2]);
+  *dt_host = c->g.cfl_dmin / smax;
+  return HYDRO_OK;
+}
+
+int hydro_step(hydro_ctx* c, double* U, double dt, const hydro_alpha* alpha_in,
+               hydro_alpha* alpha_out) {
+  if (!c || !U || !(dt >= 0.0)) return HYDRO_E_INVALID;
+  DeviceGuard dg(c->device);
+  if (!dg.ok) return HYDRO_E_DEVICE;
+  if (!alpha_in) {
+    HY_CHECK(hy::launch_clear_slots(c->ctl, c->stream));
+    HY_CHECK(hy::launch_alpha_reduce(c->g, U, c->ctl, 0, c->stream));
+  }
+  for (int s = 0; s < 3; ++s) {
+    hy::StageArgs a = stage_args(c, U, s);
+    a.dt_mode = 0;
+    a.dt_host = dt;
+    if (alpha_in) {
+      a.frozen = 1;
+      a.fax = alpha_in->ax[s];
+      a.fay = alpha_in->ay[s];
+    }
+    a.alpha_rec = alpha_out ? c->rec : nullptr;
+    HY_CHECK(launch_stage(c, a));
+  }
+  if (alpha_out) {
+    HY_CHECK(hipMemcpyAsync(c->h_buf, c->rec, 6 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HY_CHECK(hipStreamSynchronize(c->stream));
+    for (int s = 0; s < 3; ++s) {
+      alpha_out->ax[s] = c->h_buf[s];
+      alpha_out->ay[s] = c->h_buf[3 + s];
+    }
+  }
+  return HYDRO_OK;
+}
+
+int hydro_run(hydro_ctx* c, double* U, int32_t nsteps, double t_end, double* t_io, double* dt_rec,
+              double* alpha_rec) {
+  if (!c || !U || nsteps < 0) return HYDRO_E_INVALID;
+  DeviceGuard dg(c->device);
+  if (!dg.ok) return HYDRO_E_DEVICE;
+  const double t0 = t_io ? *t_io : 0.0;
+  hipLaunchKernelGGL(set_ctl_kernel, dim3(1), dim3(64), 0, c->stream, c->ctl, t0);
+  HY_CHECK(hipGetLastError());
+  HY_CHECK(hy::launch_clear_slots(c->ctl, c->stream));
+  HY_CHECK(hy::launch_alpha_reduce(c->g, U, c->ctl, 0, c->stream));
+  for (int k = 0; k < nsteps; ++k) {
+    for (int s = 0; s < 3; ++s) {
+      hy::StageArgs a = stage_args(c, U, s);
+      a.dt_mode = 1;
+      a.t_end = t_end;
+      a.dt_rec = dt_rec ? dt_rec + k : nullptr;
+      a.alpha_rec = alpha_rec ? alpha_rec + 6 * (size_t)k : nullptr;
+      HY_CHECK(launch_stage(c, a));
+    }
+  }
+  int rc = read_flag(c, false);
+  if (t_io) *t_io = c->h_ctl->t;
+  if (rc) return rc;
+  return c->h_ctl->steps;
+}
+
+int hydro_rhs(hydro_ctx* c, const double* V, double ax, double ay, double* L) {
+  if (!c || !V || !L || V == L) return HYDRO_E_INVALID;
+  DeviceGuard dg(c->device);
+  if (!dg.ok) return HYDRO_E_DEVICE;
+  hy::StageArgs a{};
+  a.g = c->g;
+  a.U0 = V;
+  a.V = V;
+  a.W = L;
+  a.rhs_only = 1;
+  a.frozen = 1;
+  a.fax = ax;
+  a.fay = ay;
+  a.ctl = c->ctl;
+  HY_CHECK(launch_stage(c, a));
+  return HYDRO_OK;
+}
+
+int hydro_step_vjp(hydro_ctx* c, const double* U_n, double dt, const hydro_alpha* alpha,
+                   const double* lam_next, double* lam_prev) {
+  if (!c || !U_n || !alpha || !lam_next || !lam_prev) return HYDRO_E_INVALID;
+  if (lam_prev == lam_next || lam_prev == U_n || !(dt >= 0.0)) return HYDRO_E_INVALID;
+  if (c->g.floor_on) return HYDRO_E_INVALID;
+  DeviceGuard dg(c->device);
+  if (!dg.ok) return HYDRO_E_DEVICE;
+  // Recompute the stage states with the recorded speeds.
+  double* R1 = c->X[0];
+  double* R2 = c->X[1];
+  double* lam2 = c->X[2];
+  double* lam1 = c->X[3];
+  for (int s = 0; s < 2; ++s) {
+    hy::StageArgs a{};
+    a.g = c->g;
+    a.U0 = U_n;
+    a.V = s == 0 ? U_n : R1;
+    a.W = s == 0 ? R1 : R2;
+    a.b = kStageWeight[s];
+    a.stage = s;
+    a.frozen = 1;
+    a.fax = alpha->ax[s];
+    a.fay = alpha->ay[s];
+    a.dt_mode = 0;
+    a.dt_host = dt;
+    a.ctl = c->ctl;
+    HY_CHECK(launch_stage(c, a));
+  }
+  // Stage adjoints, last to first.  With W = U0 + b ((V - U0) + dt L(V)):
+  //   dJ/dV  = b (lam + dt J_L(V)^T lam),  dJ/dU0 += (1 - b) lam.
+  hy::VjpArgs v{};
+  v.g = c->g;
+  v.dt = dt;
+  v.fp32 = c->p.precision == HYDRO_FP32_BULK;
+  v.ghost = c->ghost;
+  // stage 3 (input R2): lam2 = 2/3 (lam3 + dt J^T lam3);  lam_prev = 1/3 lam3
+  v.V = R2; v.lam = lam_next; v.b = kStageWeight[2]; v.ax = alpha->ax[2]; v.ay = alpha->ay[2];
+  v.out = lam2; v.acc = nullptr; v.side = lam_prev; v.side_in = nullptr;
+  HY_CHECK(hy::launch_stage_vjp(v, c->stream));
+  // stage 2 (input R1): lam1 = 1/4 (lam2 + dt J^T lam2);  lam_prev += 3/4 lam2
+  v.V = R1; v.lam = lam2; v.b = kStageWeight[1]; v.ax = alpha->ax[1]; v.ay = alpha->ay[1];
+  v.out = lam1; v.acc = nullptr; v.side = lam_prev; v.side_in = lam_prev;
+  HY_CHECK(hy::launch_stage_vjp(v, c->stream));
+  // stage 1 (input U_n = U0, b = 1): lam_prev += lam1 + dt J^T lam1
+  v.V = U_n; v.lam = lam1; v.b = kStageWeight[0]; v.ax = alpha->ax[0]; v.ay = alpha->ay[0];
+  v.out = lam_prev; v.acc = lam_prev; v.side = nullptr; v.side_in = nullptr;
+  HY_CHECK(hy::launch_stage_vjp(v, c->stream));
+  return HYDRO_OK;
+}
+
+int hydro_sums(hydro_ctx* c, const double* U, double out_host[4]) {
+  if (!c || !U || !out_host) return HYDRO_E_INVALID;
+  DeviceGuard dg(c->device);
+  if (!dg.ok) return HYDRO_E_DEVICE;
+  HY_CHECK(hy::launch_sums(c->g, U, c->partial, c->nsum, c->sum_out, c->stream));
+  HY_CHECK(hipMemcpyAsync(c->h_buf, c->sum_out, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HY_CHECK(hipStreamSynchronize(c->stream));
+  for (int k = 0; k < 4; ++k) out_host[k] = c->h_buf[k];
+  return HYDRO_OK;
+}
+
+int hydro_check(hydro_ctx* c) {
+  if (!c) return HYDRO_E_INVALID;
+  DeviceGuard dg(c->device);
+  if (!dg.ok) return HYDRO_E_DEVICE;
+  return read_flag(c, true);
+}
+
+const char* hydro_strerror(int code) {
+  switch (code) {
+    case HYDRO_OK: return "ok";
+    case HYDRO_E_INVALID: return "invalid argument";
+    case HYDRO_E_NOMEM: return "device allocation failed";
+    case HYDRO_E_DEVICE: return "HIP runtime error";
+    case HYDRO_E_UNPHYSICAL: return "unphysical state (rho <= 0 or p <= 0)";
+    case HYDRO_E_STATE: return "invalid context state";
+    default: return "unknown error";
+  }
+}
+
+}  // extern "C"

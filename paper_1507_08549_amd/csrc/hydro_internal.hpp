@@ -1,0 +1,77 @@
+// hydro_internal.hpp -- structures shared by the host side of the library and
+// its HIP kernels.  Not part of the public ABI (include/hydro.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hy {
+
+constexpr int NG = 3;  // ghost layers: a five-point WENO stencil reaches 3 cells past a face
+
+enum Bc : int { PERIODIC = 0, TRANSMISSIVE = 1, REFLECTING = 2 };
+
+// Problem constants in the form the kernels use them.  Every derived value is
+// computed once on the host with the same IEEE operations a direct
+// evaluation would use (e.g. idx = 1.0 / dx), so device results do not
+// depend on where a constant was formed.
+struct Geom {
+  int nx, ny;
+  int has_y;             // ny > 1
+  int bc[4];             // x-low, x-high, y-low, y-high
+  int cyl;               // cylindrical (r, z): geometric sources
+  double dx, dy, idx, idy;
+  double xlo;
+  double gamma, gm1, eps;
+  double gx, gy;         // uniform gravity (when grav == nullptr)
+  const double* grav;    // [2][ny][nx] or nullptr
+  int floor_on;
+  double rho_floor, p_floor, e_floor;  // e_floor = p_floor / (gamma - 1)
+  double cfl_dmin;       // cfl * min(dx, dy) (dx in 1D)
+};
+
+// Device-resident control block of a context.
+// slot[k] holds the maxima (|u|+c, |v|+c, c+|u|+|v|) of one state as the bit
+// patterns of non-negative doubles (their integer order is their numeric
+// order, so atomicMax on the bits is an exact max).  The three slots form a
+// ring over the Runge-Kutta stages: stage k reads slot k % 3 (its input's
+// speeds), accumulates its output's speeds into slot (k + 1) % 3 and clears
+// slot (k + 2) % 3 for the stage after it.
+struct Ctl {
+  unsigned long long slot[3][4];
+  double dt;     // time step of the current step (device-computed mode)
+  double t;      // time reached
+  int active;    // current step is taken (t < t_end)
+  int steps;     // steps taken by hydro_run
+  int flag;      // sticky: a stage produced rho <= 0 or p <= 0
+  int pad;
+};
+
+struct StageArgs {
+  Geom g;
+  const double* U0;   // state at the start of the step
+  const double* V;    // stage input
+  double* W;          // stage output (may alias U0: each cell reads U0 only at itself)
+  double b;           // stage weight: W = U0 + b ((V - U0) + dt L(V))
+  int stage;          // 0, 1, 2
+  int frozen;         // use fax, fay instead of the slot
+  double fax, fay;
+  int dt_mode;        // 0: dt_host; 1: computed on the device from slot 0 (stage 0)
+  double dt_host;
+  double t_end;       // clamp of the device-computed step (<= 0: none)
+  Ctl* ctl;
+  double* dt_rec;     // device mode: this step's record, or nullptr
+  double* alpha_rec;  // [6] for this step (ax[3], ay[3]), or nullptr
+  int rhs_only;       // write L(V) to W instead of a stage
+};
+
+// Launchers (defined next to their kernels).
+hipError_t launch_stage_fp64(const StageArgs& a, hipStream_t s);
+hipError_t launch_stage_fp32(const StageArgs& a, hipStream_t s);
+hipError_t launch_clear_slots(Ctl* ctl, hipStream_t s);
+hipError_t launch_alpha_reduce(const Geom& g, const double* U, Ctl* ctl, int slot, hipStream_t s);
+hipError_t launch_sums(const Geom& g, const double* U, double* partial, int nblocks, double* out,
+                       hipStream_t s);
+int sums_blocks(const Geom& g);
+
+}  // namespace hy

@@ -1,0 +1,446 @@
+// stage_kernel.hpp -- the fused Runge-Kutta stage kernel (forward), templated on
+// the arithmetic type of the spatial operator.
+//
+// One workgroup owns a TX x TY tile of cells.  It stages the tile plus three
+// ghost layers on each side (a "cross": x-halo on the tile's rows, y-halo on
+// its columns; boundary conditions applied while loading) in LDS, and then,
+// without touching HBM again until the store:
+//   1. primitive variables and the globally Lax-Friedrichs split fluxes
+//      f+- = (F(U) +- alpha_x U) / 2 of every x-point (Sect. 2.1),
+//   2. WENO5 reconstruction at every x-face of the tile, one (face, component)
+//      per work item: F^ = W(f+ upwind-left) + W(f- upwind-right),
+//   3. the same in y with alpha_y (skipped in the 1D limit),
+//   4. per cell: divergence, sources of Eq. euler2D (gravity, cylindrical
+//      geometric terms), the SSP-RK3 stage combination in FP64, the optional
+//      atmosphere floors, the positivity check, and the maxima of |u|+c, |v|+c,
+//      c+|u|+|v| of the new state, reduced across the workgroup and merged
+//      with one atomic max per quantity: the next stage's global LF speeds and
+//      the next step's CFL speed cost no extra pass over the grid.
+//
+// With R = double every formula below is evaluated with the same IEEE
+// operations in the same order as the CPU oracle's (fma where it uses fma,
+// nothing else fused: the FP64 translation unit is built with
+// -ffp-contract=off), so the two agree bit for bit.  With R = float
+// (HYDRO_FP32_BULK) the spatial operator is evaluated in FP32 with hardware
+// reciprocal/sqrt approximations and free contraction; states, the stage
+// combination and the reductions stay FP64.
+#pragma once
+
+#include "hydro_internal.hpp"
+
+namespace hy {
+
+__device__ __forceinline__ double as_double(unsigned long long b) { return __longlong_as_double((long long)b); }
+__device__ __forceinline__ unsigned long long as_bits(double d) {
+  return (unsigned long long)__double_as_longlong(d);
+}
+
+// Index of the source cell of (possibly ghost) index gi on an axis of n cells,
+// and whether the momentum normal to that axis changes sign (reflecting).
+// Indices beyond the three ghost layers only occur for tile cells past the
+// grid edge, whose results are discarded; they are clamped into range.
+__device__ __forceinline__ int map_index(int gi, int n, int lo, int hi, bool& flip) {
+  flip = false;
+  int s = gi;
+  if (gi < 0) {
+    if (lo == PERIODIC) s = gi + n;
+    else if (lo == TRANSMISSIVE) s = 0;
+    else { s = -gi - 1; flip = true; }
+  } else if (gi >= n) {
+    if (hi == PERIODIC) s = gi - n;
+    else if (hi == TRANSMISSIVE) s = n - 1;
+    else { s = 2 * n - 1 - gi; flip = true; }
+  }
+  s = s < 0 ? 0 : (s >= n ? n - 1 : s);
+  return s;
+}
+
+template <typename R> struct Prim { R u, v, p, c; };
+
+// ---------------------------------------------------------------- FP64 path
+// Same operations, same order as the oracle.
+
+__device__ __forceinline__ Prim<double> prim(double r, double mx, double my, double E,
+                                             double gamma, double gm1) {
+  Prim<double> w;
+  double rinv = 1.0 / r;
+  w.u = mx * rinv;
+  w.v = my * rinv;
+  double ke2 = mx * w.u + my * w.v;
+  w.p = gm1 * (E - 0.5 * ke2);
+  w.c = __builtin_sqrt((gamma * w.p) * rinv);
+  return w;
+}
+
+// WENO5-JS at the right face of v2, one division (weights over the common
+// denominator 10 s0 s1 s2, s_k = (eps + beta_k)^2).
+__device__ __forceinline__ double weno5(double v0, double v1, double v2, double v3, double v4,
+                                        double eps) {
+  const double c1312 = 13.0 / 12.0;
+  double d = __builtin_fma(-2.0, v1, v0) + v2;
+  double e = __builtin_fma(3.0, v2, __builtin_fma(-4.0, v1, v0));
+  double b0 = __builtin_fma(c1312 * d, d, (0.25 * e) * e);
+  d = __builtin_fma(-2.0, v2, v1) + v3;
+  e = v1 - v3;
+  double b1 = __builtin_fma(c1312 * d, d, (0.25 * e) * e);
+  d = __builtin_fma(-2.0, v3, v2) + v4;
+  e = __builtin_fma(-4.0, v3, 3.0 * v2) + v4;
+  double b2 = __builtin_fma(c1312 * d, d, (0.25 * e) * e);
+  double p0 = __builtin_fma(11.0, v2, __builtin_fma(-7.0, v1, 2.0 * v0));
+  double p1 = __builtin_fma(5.0, v2, __builtin_fma(2.0, v3, -v1));
+  double p2 = __builtin_fma(5.0, v3, __builtin_fma(2.0, v2, -v4));
+  double s0 = (eps + b0) * (eps + b0);
+  double s1 = (eps + b1) * (eps + b1);
+  double s2 = (eps + b2) * (eps + b2);
+  double w0 = s1 * s2;
+  double w1 = 6.0 * (s0 * s2);
+  double w2 = 3.0 * (s0 * s1);
+  double num = __builtin_fma(w2, p2, __builtin_fma(w1, p1, w0 * p0));
+  double den = 6.0 * ((w0 + w1) + w2);
+  return num / den;
+}
+
+__device__ __forceinline__ double lf_fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// ---------------------------------------------------------------- FP32 path
+
+__device__ __forceinline__ float rcpf(float x) { return __builtin_amdgcn_rcpf(x); }
+
+__device__ __forceinline__ Prim<float> prim(float r, float mx, float my, float E, float gamma,
+                                            float gm1) {
+  Prim<float> w;
+  float rinv = rcpf(r);
+  w.u = mx * rinv;
+  w.v = my * rinv;
+  w.p = gm1 * (E - 0.5f * (mx * w.u + my * w.v));
+  w.c = __builtin_amdgcn_sqrtf(gamma * w.p * rinv);
+  return w;
+}
+
+// Textbook weights a_k = d_k / s_k with hardware reciprocals (no overflow of
+// the products in single precision).
+__device__ __forceinline__ float weno5(float v0, float v1, float v2, float v3, float v4, float eps) {
+  const float c1312 = 13.0f / 12.0f;
+  float d = v0 - 2.0f * v1 + v2, e = v0 - 4.0f * v1 + 3.0f * v2;
+  float b0 = c1312 * d * d + 0.25f * e * e;
+  d = v1 - 2.0f * v2 + v3;
+  e = v1 - v3;
+  float b1 = c1312 * d * d + 0.25f * e * e;
+  d = v2 - 2.0f * v3 + v4;
+  e = 3.0f * v2 - 4.0f * v3 + v4;
+  float b2 = c1312 * d * d + 0.25f * e * e;
+  float s0 = eps + b0, s1 = eps + b1, s2 = eps + b2;
+  float a0 = 0.1f * rcpf(s0 * s0);
+  float a1 = 0.6f * rcpf(s1 * s1);
+  float a2 = 0.3f * rcpf(s2 * s2);
+  float p0 = 2.0f * v0 - 7.0f * v1 + 11.0f * v2;
+  float p1 = -v1 + 5.0f * v2 + 2.0f * v3;
+  float p2 = 2.0f * v2 + 5.0f * v3 - v4;
+  return (a0 * p0 + a1 * p1 + a2 * p2) * (rcpf(a0 + a1 + a2) * (1.0f / 6.0f));
+}
+
+__device__ __forceinline__ float lf_fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// ---------------------------------------------------------- split fluxes
+
+// f+- = (F(U) +- alpha U) / 2 in direction DIR (0: x, 1: y).
+template <int DIR, typename R>
+__device__ __forceinline__ void split_flux(const R U[4], R gamma, R gm1, R alpha, R fp[4], R fm[4]) {
+  Prim<R> w = prim(U[0], U[1], U[2], U[3], gamma, gm1);
+  R F[4];
+  if (DIR == 0) {
+    F[0] = U[1];
+    F[1] = lf_fma(U[1], w.u, w.p);
+    F[2] = U[2] * w.u;
+    F[3] = (U[3] + w.p) * w.u;
+  } else {
+    F[0] = U[2];
+    F[1] = U[1] * w.v;
+    F[2] = lf_fma(U[2], w.v, w.p);
+    F[3] = (U[3] + w.p) * w.v;
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    fp[c] = R(0.5) * lf_fma(alpha, U[c], F[c]);
+    fm[c] = R(0.5) * lf_fma(-alpha, U[c], F[c]);
+  }
+}
+
+// Block index -> tile index.  Workgroups are dispatched round-robin over the
+// 8 XCDs; remapping so that each XCD receives a contiguous run of tiles
+// (whole tile rows) keeps neighbouring tiles' shared halo rows in the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  if (nb % 8 != 0) return b;
+  return (b % 8) * (nb / 8) + b / 8;
+}
+
+template <typename R, int TX, int TY, bool HASY>
+__global__ __launch_bounds__(TX* TY) void stage_kernel(StageArgs a) {
+  constexpr int NT = TX * TY;
+  constexpr int GY = HASY ? NG : 0;
+  constexpr int TXP = TX + 2 * NG;
+  constexpr int TYP = TY + 2 * GY;
+  constexpr int NPX = TY * TXP;
+  constexpr int NPY = HASY ? TYP * TX : 0;
+  constexpr int NP = NPX > NPY ? NPX : NPY;
+  constexpr int NFX = TY * (TX + 1);
+  constexpr int NFY = HASY ? (TY + 1) * TX : 0;
+  constexpr int NF = NFX > NFY ? NFX : NFY;
+  constexpr int NW = (NT + 63) / 64;
+  static_assert(NT % 64 == 0, "whole wavefronts");
+
+  __shared__ R sU[4][TYP * TXP];
+  __shared__ R sF[8][NP];
+  __shared__ R sFh[4][NF];
+  __shared__ double sRed[NW][3];
+
+  const Geom& g = a.g;
+  Ctl* ctl = a.ctl;
+  const int tid = threadIdx.x;
+  const bool lead = (blockIdx.x == 0 && tid == 0);
+
+  // ---- time step and whether this step is taken
+  double dt = a.dt_host;
+  bool active = true;
+  if (!a.rhs_only && a.dt_mode == 1) {
+    if (a.stage == 0) {
+      double t = ctl->t;
+      active = !(a.t_end > 0.0) || (t < a.t_end);
+      double smax = as_double(ctl->slot[0][2]);
+      dt = g.cfl_dmin / smax;
+      if (a.t_end > 0.0 && t + dt > a.t_end) dt = a.t_end - t;
+      if (lead) {
+        ctl->active = active ? 1 : 0;
+        ctl->dt = dt;
+        if (active && a.dt_rec) *a.dt_rec = dt;
+      }
+    } else {
+      dt = ctl->dt;
+      active = ctl->active != 0;
+    }
+  }
+  if (!active) return;
+
+  // ---- LF speeds of this stage's input
+  double ax, ay;
+  if (a.frozen || a.rhs_only) {
+    ax = a.fax;
+    ay = a.fay;
+  } else {
+    ax = as_double(ctl->slot[a.stage][0]);
+    ay = as_double(ctl->slot[a.stage][1]);
+  }
+  if (lead && !a.rhs_only) {
+    const int s = a.stage;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) ctl->slot[(s + 2) % 3][k] = 0ull;
+    if (a.alpha_rec) {
+      a.alpha_rec[s] = ax;
+      a.alpha_rec[3 + s] = ay;
+    }
+    if (s == 2 && a.dt_mode == 1) {
+      ctl->t = ctl->t + dt;
+      ctl->steps = ctl->steps + 1;
+    }
+  }
+
+  const int ntx = (g.nx + TX - 1) / TX;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int i0 = (tile % ntx) * TX;
+  const int j0 = (tile / ntx) * TY;
+  const size_t n = (size_t)g.nx * g.ny;
+  const R gamma = (R)g.gamma, gm1 = (R)g.gm1, eps = (R)g.eps;
+
+  // ---- 1. stage the tile and its halo cross in LDS (boundary conditions here)
+  for (int k = tid; k < TYP * TXP; k += NT) {
+    const int ly = k / TXP, lx = k - ly * TXP;
+    const bool inx = lx >= NG && lx < NG + TX;
+    const bool iny = ly >= GY && ly < GY + TY;
+    if (!inx && !iny) continue;  // corners: not on any stencil
+    bool fx, fy = false;
+    const int si = map_index(i0 + lx - NG, g.nx, g.bc[0], g.bc[1], fx);
+    const int sj = HASY ? map_index(j0 + ly - GY, g.ny, g.bc[2], g.bc[3], fy) : 0;
+    const size_t q = (size_t)sj * g.nx + si;
+    const double r = a.V[q], mx = a.V[n + q], my = a.V[2 * n + q], E = a.V[3 * n + q];
+    sU[0][k] = (R)r;
+    sU[1][k] = (R)(fx ? -mx : mx);
+    sU[2][k] = (R)(fy ? -my : my);
+    sU[3][k] = (R)E;
+  }
+  __syncthreads();
+
+  const int tx = tid % TX, ty = tid / TX;
+  R D[4];
+
+  // ---- 2. x sweep
+  {
+    const R al = (R)ax;
+    for (int k = tid; k < NPX; k += NT) {
+      const int j = k / TXP, lx = k - j * TXP;
+      const int src = (j + GY) * TXP + lx;
+      R U[4] = {sU[0][src], sU[1][src], sU[2][src], sU[3][src]};
+      R fp[4], fm[4];
+      split_flux<0>(U, gamma, gm1, al, fp, fm);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        sF[c][k] = fp[c];
+        sF[4 + c][k] = fm[c];
+      }
+    }
+    __syncthreads();
+    for (int t = tid; t < 4 * NFX; t += NT) {
+      const int f = t % (TX + 1);
+      const int rest = t / (TX + 1);
+      const int j = rest % TY, c = rest / TY;
+      const R* P = &sF[c][j * TXP + f];
+      const R* M = &sF[4 + c][j * TXP + f];
+      const R wp = weno5(P[0], P[1], P[2], P[3], P[4], eps);
+      const R wm = weno5(M[5], M[4], M[3], M[2], M[1], eps);
+      sFh[c][j * (TX + 1) + f] = wp + wm;
+    }
+    __syncthreads();
+    const R idx = (R)g.idx;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      D[c] = (sFh[c][ty * (TX + 1) + tx + 1] - sFh[c][ty * (TX + 1) + tx]) * idx;
+  }
+
+  // ---- 3. y sweep
+  R Dy[4] = {R(0), R(0), R(0), R(0)};
+  if (HASY) {
+    __syncthreads();  // sF / sFh are reused
+    const R al = (R)ay;
+    for (int k = tid; k < NPY; k += NT) {
+      const int ly = k / TX, i = k - ly * TX;
+      const int src = ly * TXP + i + NG;
+      R U[4] = {sU[0][src], sU[1][src], sU[2][src], sU[3][src]};
+      R fp[4], fm[4];
+      split_flux<1>(U, gamma, gm1, al, fp, fm);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        sF[c][k] = fp[c];
+        sF[4 + c][k] = fm[c];
+      }
+    }
+    __syncthreads();
+    for (int t = tid; t < 4 * NFY; t += NT) {
+      const int i = t % TX;
+      const int rest = t / TX;
+      const int f = rest % (TY + 1), c = rest / (TY + 1);
+      const R* P = &sF[c][f * TX + i];
+      const R* M = &sF[4 + c][f * TX + i];
+      const R wp = weno5(P[0], P[TX], P[2 * TX], P[3 * TX], P[4 * TX], eps);
+      const R wm = weno5(M[5 * TX], M[4 * TX], M[3 * TX], M[2 * TX], M[TX], eps);
+      sFh[c][f * TX + i] = wp + wm;
+    }
+    __syncthreads();
+    const R idy = (R)g.idy;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) Dy[c] = (sFh[c][(ty + 1) * TX + tx] - sFh[c][ty * TX + tx]) * idy;
+  }
+
+  // ---- 4. per cell: sources, L, stage combination, floor, check, maxima
+  const int I = i0 + tx, J = j0 + ty;
+  const bool act = I < g.nx && J < g.ny;
+  double amax = 0.0, bmax = 0.0, smax = 0.0;
+  bool bad = false;
+  if (act) {
+    const size_t q = (size_t)J * g.nx + I;
+    const int cs = (ty + GY) * TXP + tx + NG;
+    const R r = sU[0][cs], mx = sU[1][cs], my = sU[2][cs], E = sU[3][cs];
+    const R gxv = g.grav ? (R)g.grav[q] : (R)g.gx;
+    const R gyv = g.grav ? (R)g.grav[n + q] : (R)g.gy;
+    R S[4];
+    S[0] = R(0);
+    S[1] = r * gxv;
+    S[2] = r * gyv;
+    S[3] = mx * gxv + my * gyv;
+    if (g.cyl) {
+      const Prim<R> w = prim(r, mx, my, E, gamma, gm1);
+      const double ri = g.xlo + ((double)I + 0.5) * g.dx;
+      const R ir = (R)(1.0 / ri);
+      S[0] = S[0] - ir * mx;
+      S[1] = S[1] - ir * (mx * w.u);
+      S[2] = S[2] - ir * (my * w.u);
+      S[3] = S[3] - ir * ((E + w.p) * w.u);
+    }
+    R L[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) L[c] = HASY ? S[c] - (D[c] + Dy[c]) : S[c] - D[c];
+    if (a.rhs_only) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) a.W[c * n + q] = (double)L[c];
+    } else {
+      double w[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const double v = a.V[c * n + q];
+        const double u0 = a.U0[c * n + q];
+        w[c] = __builtin_fma(a.b, __builtin_fma(dt, (double)L[c], v - u0), u0);
+      }
+      if (g.floor_on) {  // atmosphere: minimum density, then minimum pressure
+        if (w[0] < g.rho_floor) {
+          w[0] = g.rho_floor;
+          w[1] = 0.0;
+          w[2] = 0.0;
+          w[3] = g.e_floor;
+        }
+        const Prim<double> pf = prim(w[0], w[1], w[2], w[3], g.gamma, g.gm1);
+        if (pf.p < g.p_floor) w[3] = g.e_floor + 0.5 * (w[1] * pf.u + w[2] * pf.v);
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) a.W[c * n + q] = w[c];
+      const Prim<double> pw = prim(w[0], w[1], w[2], w[3], g.gamma, g.gm1);
+      bad = !(w[0] > 0.0) || !(pw.p > 0.0) || !__builtin_isfinite(pw.c);
+      amax = __builtin_fabs(pw.u) + pw.c;
+      bmax = __builtin_fabs(pw.v) + pw.c;
+      smax = pw.c + (__builtin_fabs(pw.u) + __builtin_fabs(pw.v));
+    }
+  }
+  if (a.rhs_only) return;
+
+  // ---- maxima: wavefront shuffles, then LDS across the workgroup's waves,
+  // then one atomic max per quantity (exact and order-free).
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    amax = __builtin_fmax(amax, __shfl_xor(amax, off));
+    bmax = __builtin_fmax(bmax, __shfl_xor(bmax, off));
+    smax = __builtin_fmax(smax, __shfl_xor(smax, off));
+  }
+  const int wave = tid / 64;
+  if ((tid & 63) == 0) {
+    sRed[wave][0] = amax;
+    sRed[wave][1] = bmax;
+    sRed[wave][2] = smax;
+  }
+  const int anybad = __syncthreads_or(bad ? 1 : 0);
+  if (tid == 0) {
+    for (int k = 1; k < NW; ++k) {
+      amax = __builtin_fmax(amax, sRed[k][0]);
+      bmax = __builtin_fmax(bmax, sRed[k][1]);
+      smax = __builtin_fmax(smax, sRed[k][2]);
+    }
+    unsigned long long* slot = ctl->slot[(a.stage + 1) % 3];
+    atomicMax(&slot[0], as_bits(amax));
+    atomicMax(&slot[1], as_bits(bmax));
+    atomicMax(&slot[2], as_bits(smax));
+    if (anybad) atomicOr(&ctl->flag, 1);
+  }
+}
+
+// Tile shapes: 16 x 16 cells (256 work items) in 2D; 256 x 1 in the 1D limit.
+template <typename R>
+hipError_t launch_stage(const StageArgs& a, hipStream_t s) {
+  if (a.g.has_y) {
+    constexpr int TX = 16, TY = 16;
+    const int nb = ((a.g.nx + TX - 1) / TX) * ((a.g.ny + TY - 1) / TY);
+    hipLaunchKernelGGL((stage_kernel<R, TX, TY, true>), dim3(nb), dim3(TX * TY), 0, s, a);
+  } else {
+    constexpr int TX = 256, TY = 1;
+    const int nb = (a.g.nx + TX - 1) / TX;
+    hipLaunchKernelGGL((stage_kernel<R, TX, TY, false>), dim3(nb), dim3(TX * TY), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace hy

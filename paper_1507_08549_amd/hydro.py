@@ -1,0 +1,245 @@
+"""Python binding of the HIP library (include/hydro.h): argument marshalling only.
+
+Every computation runs in the library's kernels; PyTorch supplies device
+memory (float64 CUDA/HIP tensors of shape (4, ny, nx), components
+rho, m_x, m_y, E) and the stream.  If the library is not built, or no GPU is
+present, constructing a :class:`Solver` raises -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhydro.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "hydro.h")
+
+HYDRO_OK, HYDRO_E_INVALID, HYDRO_E_NOMEM, HYDRO_E_DEVICE, HYDRO_E_UNPHYSICAL, HYDRO_E_STATE = \
+    0, -1, -2, -3, -4, -5
+PERIODIC, TRANSMISSIVE, REFLECTING = 0, 1, 2
+CARTESIAN, CYLINDRICAL = 0, 1
+FP64, FP32_BULK = 0, 1
+
+
+class HydroError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        msg = load().hydro_strerror(code).decode() if _lib is not None else str(code)
+        super().__init__(f"{where}: {msg} ({code})")
+
+
+class UnphysicalError(HydroError):
+    pass
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("xlo", ctypes.c_double), ("xhi", ctypes.c_double),
+        ("ylo", ctypes.c_double), ("yhi", ctypes.c_double),
+        ("geometry", ctypes.c_int32), ("bc", ctypes.c_int32 * 4),
+        ("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("weno_eps", ctypes.c_double),
+        ("precision", ctypes.c_int32),
+        ("gx", ctypes.c_double), ("gy", ctypes.c_double),
+        ("rho_floor", ctypes.c_double), ("p_floor", ctypes.c_double),
+    ]
+
+
+class Alpha(ctypes.Structure):
+    _fields_ = [("ax", ctypes.c_double * 3), ("ay", ctypes.c_double * 3)]
+
+
+_lib = None
+
+#: names of the entry points declared in include/hydro.h
+ENTRY_POINTS = ("hydro_create", "hydro_destroy", "hydro_cfl", "hydro_step", "hydro_run",
+                "hydro_rhs", "hydro_step_vjp", "hydro_sums", "hydro_check", "hydro_strerror")
+
+
+def declared_entry_points(header: str = HEADER):
+    """Function names declared in the public header (for the ABI tests)."""
+    src = open(header).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hydro_[a-z_]+)\s*\(", src)))
+
+
+def load():
+    """Load libhydro.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1507_08549_amd.build.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int
+    lib.hydro_create.argtypes = [ctypes.POINTER(Params), vp, vp, ctypes.POINTER(vp)]
+    lib.hydro_destroy.argtypes = [vp]
+    lib.hydro_cfl.argtypes = [vp, vp, dp]
+    lib.hydro_step.argtypes = [vp, vp, ctypes.c_double, ctypes.POINTER(Alpha), ctypes.POINTER(Alpha)]
+    lib.hydro_run.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_double, dp, vp, vp]
+    lib.hydro_rhs.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double, vp]
+    lib.hydro_step_vjp.argtypes = [vp, vp, ctypes.c_double, ctypes.POINTER(Alpha), vp, vp]
+    lib.hydro_sums.argtypes = [vp, vp, dp]
+    lib.hydro_check.argtypes = [vp]
+    lib.hydro_strerror.argtypes = [ip]
+    lib.hydro_strerror.restype = ctypes.c_char_p
+    for f in ENTRY_POINTS:
+        if f != "hydro_strerror":
+            getattr(lib, f).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def make_params(prm: dict, precision=FP64) -> Params:
+    p = Params()
+    p.nx, p.ny = int(prm["nx"]), int(prm["ny"])
+    p.xlo, p.xhi, p.ylo, p.yhi = (float(prm[k]) for k in ("xlo", "xhi", "ylo", "yhi"))
+    p.geometry = int(prm.get("geometry", CARTESIAN))
+    for k, b in enumerate(prm["bc"]):
+        p.bc[k] = int(b)
+    p.gamma = float(prm["gamma"])
+    p.cfl = float(prm.get("cfl", 0.5))
+    p.weno_eps = float(prm.get("eps", 1e-6))
+    p.precision = int(precision)
+    p.gx, p.gy = float(prm.get("gx", 0.0)), float(prm.get("gy", 0.0))
+    p.rho_floor = float(prm.get("rho_floor", 0.0))
+    p.p_floor = float(prm.get("p_floor", 0.0))
+    return p
+
+
+def _alpha_struct(alpha):
+    if alpha is None:
+        return None
+    a = np.asarray(alpha, dtype=np.float64).reshape(3, 2)
+    s = Alpha()
+    for k in range(3):
+        s.ax[k], s.ay[k] = float(a[k, 0]), float(a[k, 1])
+    return s
+
+
+def _alpha_array(s: Alpha):
+    return np.array([[s.ax[k], s.ay[k]] for k in range(3)])
+
+
+class Solver:
+    """One library context: a problem description bound to a device and stream.
+
+    ``params`` is the dict produced by :mod:`paper_1507_08549_amd.inputs`;
+    ``gravity`` an optional (2, ny, nx) float64 device tensor (kept alive by
+    the solver); ``precision`` FP64 or FP32_BULK."""
+
+    def __init__(self, params: dict, gravity=None, precision=FP64, device=None):
+        import torch
+        lib = load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the hydro library runs on the device only")
+        self.torch = torch
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.params = dict(params)
+        self.nx, self.ny = int(params["nx"]), int(params["ny"])
+        self.precision = precision
+        self.gravity = None
+        gptr = None
+        if gravity is not None:
+            g = torch.as_tensor(gravity, dtype=torch.float64, device=self.device).contiguous()
+            if tuple(g.shape) != (2, self.ny, self.nx):
+                raise ValueError(f"gravity must have shape (2, {self.ny}, {self.nx})")
+            self.gravity = g
+            gptr = g.data_ptr()
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+            self._p = make_params(params, precision)
+            h = ctypes.c_void_p()
+            rc = lib.hydro_create(ctypes.byref(self._p), gptr, self.stream.cuda_stream, ctypes.byref(h))
+        self._check(rc, "hydro_create")
+        self._h = h
+        self._lib = lib
+
+    # -- helpers
+    def _check(self, rc, where):
+        if rc == HYDRO_E_UNPHYSICAL:
+            raise UnphysicalError(rc, where)
+        if rc < 0:
+            raise HydroError(rc, where)
+        return rc
+
+    def _state(self, U, name="U"):
+        t = self.torch
+        if not isinstance(U, t.Tensor) or U.dtype != t.float64 or U.device != self.device:
+            raise TypeError(f"{name} must be a float64 tensor on {self.device}")
+        if tuple(U.shape) != (4, self.ny, self.nx) or not U.is_contiguous():
+            raise ValueError(f"{name} must be contiguous with shape (4, {self.ny}, {self.nx})")
+        return U.data_ptr()
+
+    def new_state(self):
+        return self.torch.empty((4, self.ny, self.nx), dtype=self.torch.float64, device=self.device)
+
+    # -- API
+    def cfl(self, U) -> float:
+        dt = ctypes.c_double()
+        self._check(self._lib.hydro_cfl(self._h, self._state(U), ctypes.byref(dt)), "hydro_cfl")
+        return dt.value
+
+    def step(self, U, dt, alpha=None, return_alpha=False):
+        """One SSP-RK3 step in place.  alpha: None (computed) or (3, 2) speeds."""
+        a_in = _alpha_struct(alpha)
+        a_out = Alpha() if return_alpha else None
+        rc = self._lib.hydro_step(self._h, self._state(U), float(dt),
+                                  ctypes.byref(a_in) if a_in is not None else None,
+                                  ctypes.byref(a_out) if a_out is not None else None)
+        self._check(rc, "hydro_step")
+        return _alpha_array(a_out) if return_alpha else None
+
+    def run(self, U, nsteps, t_end=0.0, t0=0.0, record=False):
+        """Up to nsteps CFL steps in place.  Returns (steps, t, dt_rec, alpha_rec);
+        the records are device tensors (or None)."""
+        t = self.torch
+        tt = ctypes.c_double(float(t0))
+        dts = als = None
+        if record:
+            dts = t.zeros(max(nsteps, 1), dtype=t.float64, device=self.device)
+            als = t.zeros((max(nsteps, 1), 6), dtype=t.float64, device=self.device)
+        rc = self._lib.hydro_run(self._h, self._state(U), int(nsteps), float(t_end), ctypes.byref(tt),
+                                 dts.data_ptr() if record else None,
+                                 als.data_ptr() if record else None)
+        k = self._check(rc, "hydro_run")
+        if record:
+            dts = dts[:k]
+            als = als[:k].reshape(k, 2, 3).transpose(1, 2)
+        return k, tt.value, dts, als
+
+    def rhs(self, V, ax, ay, out=None):
+        L = self.new_state() if out is None else out
+        self._check(self._lib.hydro_rhs(self._h, self._state(V), float(ax), float(ay),
+                                        self._state(L, "L")), "hydro_rhs")
+        return L
+
+    def step_vjp(self, U_n, dt, alpha, lam_next, out=None):
+        lam_prev = self.new_state() if out is None else out
+        a = _alpha_struct(alpha)
+        rc = self._lib.hydro_step_vjp(self._h, self._state(U_n), float(dt), ctypes.byref(a),
+                                      self._state(lam_next, "lam_next"), self._state(lam_prev, "lam_prev"))
+        self._check(rc, "hydro_step_vjp")
+        return lam_prev
+
+    def sums(self, U):
+        out = (ctypes.c_double * 4)()
+        self._check(self._lib.hydro_sums(self._h, self._state(U), out), "hydro_sums")
+        return np.array(out[:])
+
+    def check(self):
+        return self._check(self._lib.hydro_check(self._h), "hydro_check")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.hydro_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

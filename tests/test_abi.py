@@ -1,0 +1,75 @@
+"""The C-ABI library loads and exports every entry point include/hydro.h
+declares; argument checks that happen before any device call behave as
+documented.  No compute calls (these run without a GPU)."""
+import ctypes
+import os
+
+import pytest
+
+from paper_1507_08549_amd import hydro, inputs
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(hydro.LIB_PATH):
+        from paper_1507_08549_amd import build
+        build.build()
+    return hydro.load()
+
+
+def test_header_declares_the_boundary():
+    names = hydro.declared_entry_points()
+    for required in ("hydro_create", "hydro_step", "hydro_cfl", "hydro_step_vjp"):
+        assert required in names
+    assert sorted(hydro.ENTRY_POINTS) == names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in hydro.declared_entry_points():
+        assert hasattr(lib, name), name
+
+
+def test_strerror_names_every_code(lib):
+    for code in range(0, -6, -1):
+        s = lib.hydro_strerror(code).decode()
+        assert s and s != "unknown error"
+    assert lib.hydro_strerror(-99).decode() == "unknown error"
+
+
+@pytest.mark.parametrize("mutate", [
+    lambda p: setattr(p, "nx", 2),
+    lambda p: setattr(p, "ny", 2),
+    lambda p: setattr(p, "gamma", 1.0),
+    lambda p: setattr(p, "weno_eps", 0.0),
+    lambda p: setattr(p, "cfl", -1.0),
+    lambda p: p.bc.__setitem__(0, 3),
+    lambda p: p.bc.__setitem__(1, hydro.REFLECTING),  # periodic on one side only
+    lambda p: setattr(p, "precision", 7),
+    lambda p: setattr(p, "xhi", p.xlo),
+    lambda p: (setattr(p, "geometry", hydro.CYLINDRICAL), setattr(p, "xlo", -1.0)),
+])
+def test_create_rejects_invalid_params(lib, mutate):
+    prm, _ = inputs.kelvin_helmholtz(16)
+    p = hydro.make_params(prm)
+    mutate(p)
+    h = ctypes.c_void_p()
+    assert lib.hydro_create(ctypes.byref(p), None, None, ctypes.byref(h)) == hydro.HYDRO_E_INVALID
+    assert not h.value
+
+
+def test_null_arguments_rejected(lib):
+    assert lib.hydro_create(None, None, None, None) == hydro.HYDRO_E_INVALID
+    assert lib.hydro_destroy(None) == hydro.HYDRO_OK
+    assert lib.hydro_cfl(None, None, None) == hydro.HYDRO_E_INVALID
+    assert lib.hydro_step(None, None, 0.1, None, None) == hydro.HYDRO_E_INVALID
+    assert lib.hydro_step_vjp(None, None, 0.1, None, None, None) == hydro.HYDRO_E_INVALID
+    assert lib.hydro_check(None) == hydro.HYDRO_E_INVALID
+
+
+def test_solver_refuses_to_run_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    prm, _ = inputs.kelvin_helmholtz(16)
+    with pytest.raises(RuntimeError):
+        hydro.Solver(prm)

@@ -1,0 +1,238 @@
+"""GPU parity: the HIP path against the FP64 oracle, through the C ABI.
+
+FP64: bit-for-bit equality (the kernels perform the oracle's IEEE operations
+in the oracle's order; see the arithmetic contract in the oracle's header).
+The tests assert exact equality and report the largest difference when it
+fails; the stated bound of the method (relative L1 <= 1e-12) is implied.
+
+Sizes: tiny grids for every boundary combination and both geometries
+(several tiles, ragged edges, grids smaller than one tile), then the full
+sizes of the workloads (shock tube 400 x 1; shear layer 512^2; heavy-over-
+light layer 256 x 1024; polytrope 1024^2 in (r, z) with a gravity field and
+the density floor; sine-mode shear layer 1024^2), a few steps each, whole
+grid compared.
+"""
+import numpy as np
+import pytest
+
+from paper_1507_08549_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+P, T, R = inputs.PERIODIC, inputs.TRANSMISSIVE, inputs.REFLECTING
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available(), "GPU tests need a GPU"
+    return _t
+
+
+@pytest.fixture(scope="module")
+def hydro():
+    from paper_1507_08549_amd import hydro as _h
+    _h.load()
+    return _h
+
+
+def _dev(torch, a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _random_state(ny, nx, seed, gamma=1.4):
+    rng = np.random.default_rng(seed)
+    rho = 1.0 + 0.5 * rng.uniform(0, 1, (ny, nx))
+    u = 0.5 * rng.uniform(-1, 1, (ny, nx))
+    v = 0.5 * rng.uniform(-1, 1, (ny, nx))
+    p = 1.0 + 0.5 * rng.uniform(0, 1, (ny, nx))
+    return inputs.state_from_primitive(rho, u, v, p, gamma)
+
+
+def _assert_same(got, want, what):
+    got = np.asarray(got)
+    if not np.array_equal(got, want):
+        d = np.abs(got - want)
+        rel = d.sum() / max(np.abs(want).sum(), 1e-300)
+        k = np.unravel_index(np.argmax(d), d.shape)
+        raise AssertionError(f"{what}: not bitwise equal; max |diff| {d.max():.3e} at {k}, "
+                             f"relative L1 {rel:.3e}")
+
+
+BCS = [[P, P, P, P], [T, T, T, T], [R, R, R, R], [R, T, R, T], [T, R, P, P]]
+SHAPES = [(8, 8), (11, 13), (16, 16), (17, 33), (70, 40)]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: f"{s[0]}x{s[1]}")
+@pytest.mark.parametrize("bc", BCS, ids=lambda b: "".join("PTR"[k] for k in b))
+@pytest.mark.parametrize("geometry", [0, 1], ids=["cart", "cyl"])
+def test_small_grids_three_steps_bitwise(torch, hydro, oracle_mod, shape, bc, geometry):
+    if geometry == 1 and bc[0] == P:
+        pytest.skip("periodic axis in cylindrical geometry")
+    ny, nx = shape
+    xlo = 0.0 if geometry == 1 else -0.3
+    prm = inputs.make_params(nx, ny, xlo, xlo + 1.0, 0.0, 0.8, bc, 1.4, cfl=0.5,
+                             geometry=geometry, gx=0.05, gy=-0.1)
+    U0 = _random_state(ny, nx, seed=nx * 100 + ny)
+    o = oracle_mod.Oracle(prm)
+    s = hydro.Solver(prm)
+    U = _dev(torch, U0)
+    want = U0.copy()
+    for k in range(3):
+        dt = o.cfl(want)
+        assert s.cfl(U) == dt
+        want, al = o.step(want, dt)
+        got_al = s.step(U, dt, return_alpha=True)
+        assert np.array_equal(got_al, al), (got_al, al)
+        _assert_same(U.cpu().numpy(), want, f"step {k}")
+
+
+@pytest.mark.parametrize("shape", [(8, 8), (17, 33), (70, 40)], ids=lambda s: f"{s[0]}x{s[1]}")
+def test_rhs_bitwise(torch, hydro, oracle_mod, shape):
+    ny, nx = shape
+    prm = inputs.make_params(nx, ny, 0.0, 1.0, 0.0, 1.0, [R, T, P, P], 5.0 / 3.0, geometry=1)
+    U0 = _random_state(ny, nx, seed=7, gamma=5.0 / 3.0)
+    o = oracle_mod.Oracle(prm)
+    s = hydro.Solver(prm)
+    L = s.rhs(_dev(torch, U0), 2.5, 3.0)
+    _assert_same(L.cpu().numpy(), o.rhs(U0, 2.5, 3.0), "L(U)")
+
+
+def test_frozen_alpha_step_bitwise(torch, hydro, oracle_mod):
+    prm, U0 = inputs.kelvin_helmholtz(48, seed=11)
+    o = oracle_mod.Oracle(prm)
+    s = hydro.Solver(prm)
+    al = np.array([[3.1, 2.9], [3.2, 3.0], [3.3, 3.05]])
+    want, _ = o.step(U0, 1e-3, al)
+    U = _dev(torch, U0)
+    s.step(U, 1e-3, alpha=al)
+    _assert_same(U.cpu().numpy(), want, "frozen-alpha step")
+
+
+@pytest.mark.parametrize("n", [5, 300, 1000], ids=lambda n: f"n{n}")
+def test_1d_limit_bitwise(torch, hydro, oracle_mod, n):
+    prm, U0 = inputs.riemann_1d(1.0, 0.75, 1.0, 0.125, 0.0, 0.1, x0=0.3, n=n, cfl=0.5)
+    o = oracle_mod.Oracle(prm)
+    s = hydro.Solver(prm)
+    want, t, dts, als = o.run(U0, 25)
+    U = _dev(torch, U0)
+    k, t_gpu, gd, ga = s.run(U, 25, record=True)
+    assert k == 25 and t_gpu == t
+    assert np.array_equal(gd.cpu().numpy(), dts)
+    assert np.array_equal(ga.cpu().numpy(), als)
+    _assert_same(U.cpu().numpy(), want, "1D run")
+
+
+def test_sod_full_run_to_t_end_bitwise(torch, hydro, oracle_mod):
+    """The shock tube of 400 cells to t = 0.2 with the device-side CFL step,
+    the last step clamped to t_end."""
+    prm, U0 = inputs.sod(400)
+    o = oracle_mod.Oracle(prm)
+    want, t, dts, _ = o.run(U0, 100000, t_end=0.2)
+    s = hydro.Solver(prm)
+    U = _dev(torch, U0)
+    k, t_gpu, gd, _ = s.run(U, len(dts) + 20, t_end=0.2, record=True)
+    assert k == len(dts) and t_gpu == t == 0.2
+    assert np.array_equal(gd.cpu().numpy(), dts)
+    _assert_same(U.cpu().numpy(), want, "Sod at t = 0.2")
+
+
+def test_kh_512_bitwise(torch, hydro, oracle_mod):
+    prm, U0 = inputs.kelvin_helmholtz(512, seed=2)
+    o = oracle_mod.Oracle(prm)
+    want, t, dts, als = o.run(U0, 3)
+    s = hydro.Solver(prm)
+    U = _dev(torch, U0)
+    k, t_gpu, gd, ga = s.run(U, 3, record=True)
+    assert np.array_equal(ga.cpu().numpy(), als)
+    _assert_same(U.cpu().numpy(), want, "KH 512^2, 3 steps")
+
+
+def test_rt_256x1024_bitwise(torch, hydro, oracle_mod):
+    prm, U0 = inputs.rayleigh_taylor(256, 1024, seed=3)
+    o = oracle_mod.Oracle(prm)
+    want, _, _, _ = o.run(U0, 2)
+    s = hydro.Solver(prm)
+    U = _dev(torch, U0)
+    s.run(U, 2)
+    _assert_same(U.cpu().numpy(), want, "RT 256x1024, 2 steps")
+
+
+def test_polytrope_1024_gravity_field_and_floor_bitwise(torch, hydro, oracle_mod):
+    prm, U0, g = inputs.polytrope(1024, seed=4)
+    o = oracle_mod.Oracle(prm, g)
+    want, _, _, _ = o.run(U0, 1)
+    s = hydro.Solver(prm, gravity=_dev(torch, g))
+    U = _dev(torch, U0)
+    s.run(U, 1)
+    _assert_same(U.cpu().numpy(), want, "polytrope 1024^2, 1 step")
+
+
+def test_polytrope_small_many_steps_bitwise(torch, hydro, oracle_mod):
+    prm, U0, g = inputs.polytrope(96, seed=4)
+    o = oracle_mod.Oracle(prm, g)
+    want, _, _, _ = o.run(U0, 30)
+    s = hydro.Solver(prm, gravity=_dev(torch, g))
+    U = _dev(torch, U0)
+    s.run(U, 30)
+    _assert_same(U.cpu().numpy(), want, "polytrope 96^2, 30 steps")
+
+
+def test_kh_sine_1024_bitwise(torch, hydro, oracle_mod):
+    prm = inputs.kh_sine_params(1024)
+    U0 = inputs.kh_sine_state(inputs.kh_sine_amplitudes(), prm)
+    o = oracle_mod.Oracle(prm)
+    want, _, _, _ = o.run(U0, 1)
+    s = hydro.Solver(prm)
+    U = _dev(torch, U0)
+    s.run(U, 1)
+    _assert_same(U.cpu().numpy(), want, "sine-mode KH 1024^2, 1 step")
+
+
+def test_kh_small_long_run_bitwise(torch, hydro, oracle_mod):
+    """200 steps of the (chaotic) shear layer on 64^2: round-off differences
+    would grow, so equality here shows the operation sequences are the same."""
+    prm, U0 = inputs.kelvin_helmholtz(64, seed=2)
+    o = oracle_mod.Oracle(prm)
+    want, t, _, _ = o.run(U0, 200)
+    s = hydro.Solver(prm)
+    U = _dev(torch, U0)
+    k, t_gpu, _, _ = s.run(U, 200)
+    assert t_gpu == t
+    _assert_same(U.cpu().numpy(), want, "KH 64^2, 200 steps")
+
+
+@pytest.mark.parametrize("geometry", [0, 1])
+def test_sums_match_oracle(torch, hydro, oracle_mod, geometry):
+    prm, U0 = inputs.kelvin_helmholtz(200, seed=3)
+    if geometry == 1:
+        prm["bc"] = [R, T, P, P]
+        prm["geometry"] = 1
+    o = oracle_mod.Oracle(prm)
+    s = hydro.Solver(prm)
+    got = s.sums(_dev(torch, U0))
+    want = o.sums(U0)
+    scale = o.sums(np.abs(U0))
+    assert np.all(np.abs(got - want) <= 4e-16 * scale), (got - want) / scale
+
+
+def test_unphysical_state_is_reported_and_cleared(torch, hydro):
+    prm, U0 = inputs.kelvin_helmholtz(32, seed=1)
+    U0 = U0.copy()
+    U0[3, 5, 7] = -1.0  # negative energy -> p < 0
+    s = hydro.Solver(prm)
+    U = _dev(torch, U0)
+    with pytest.raises(hydro.UnphysicalError):
+        s.cfl(U)
+    with pytest.raises(hydro.UnphysicalError):
+        s.check()
+    s.check()  # cleared
+
+
+def test_invalid_arguments_raise(torch, hydro):
+    prm, U0 = inputs.kelvin_helmholtz(32, seed=1)
+    s = hydro.Solver(prm)
+    with pytest.raises((TypeError, ValueError)):
+        s.step(torch.zeros((4, 31, 32), dtype=torch.float64, device="cuda"), 1e-3)
+    with pytest.raises(TypeError):
+        s.step(torch.zeros((4, 32, 32), dtype=torch.float32, device="cuda"), 1e-3)

@@ -67,6 +67,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=40,
                     help="oracle steps timed for the CPU baseline (0: skip)")
     ap.add_argument("--only-fp64", action="store_true", help="skip the FP32-bulk leg")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="also run a plain device copy of MIB MiB three times (a known-size "
+                         "kernel for calibrating the profiler's HBM byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -159,6 +162,15 @@ def main():
         "fp32_bulk": fp32,
     }
     print(json.dumps(out), flush=True)
+
+    if args.copy_probe > 0:
+        nel = args.copy_probe * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {args.copy_probe} MiB read + {args.copy_probe} MiB written per copy, 3 copies")
 
 
 if __name__ == "__main__":

@@ -102,7 +102,7 @@ typedef struct hydro_ctx hydro_ctx;
  *           (g_x, g_y) per cell; borrowed, must outlive the context.
  *  stream   a hipStream_t, or NULL for the null stream.
  *  out      receives the context.
- * Allocates 6 state-sized scratch buffers.  Errors: INVALID, NOMEM, DEVICE. */
+ * Allocates 7 state-sized scratch buffers.  Errors: INVALID, NOMEM, DEVICE. */
 int hydro_create(const hydro_params* params, const double* gravity, void* stream,
                  hydro_ctx** out);
 

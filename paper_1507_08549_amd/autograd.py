@@ -1,0 +1,86 @@
+"""Differentiable rollouts over the HIP solver (torch.autograd).
+
+:class:`HydroRollout` advances a state ``nsteps`` SSP-RK3 steps with the
+device-side CFL step, recording each step's time step and the LF speeds of
+its three stages, and keeps a checkpoint of the state every ``ckpt_every``
+steps.  Its backward pass walks the segments from last to first: it re-runs
+the segment from its checkpoint with the recorded schedule (bit-identical to
+the forward), keeping the state at the start of every step, and then applies
+``hydro_step_vjp`` step by step (each call recomputes that step's two stage
+states).  Memory: nsteps / ckpt_every checkpoints plus ckpt_every states.
+
+The gradient is that of the discrete map with the schedule (dt and alpha of
+every stage) held at its recorded values: those come from maxima over the
+grid, and are treated as constants, as in any frozen-schedule adjoint.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import hydro
+
+
+class HydroRollout(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, U0, solver: "hydro.Solver", nsteps: int, ckpt_every: int = 50):
+        if ckpt_every < 1:
+            raise ValueError("ckpt_every must be >= 1")
+        U = U0.detach().clone().contiguous()
+        dts = torch.empty(max(nsteps, 1), dtype=torch.float64, device=U.device)
+        als = torch.empty((max(nsteps, 1), 6), dtype=torch.float64, device=U.device)
+        ckpts = []
+        for s0 in range(0, nsteps, ckpt_every):
+            k = min(ckpt_every, nsteps - s0)
+            ckpts.append(U.clone())
+            solver.run_into(U, k, dts[s0:s0 + k], als[s0:s0 + k])
+        ctx.solver = solver
+        ctx.nsteps = nsteps
+        ctx.ckpt_every = ckpt_every
+        ctx.ckpts = ckpts
+        ctx.sched = (dts[:nsteps], als[:nsteps])
+        return U
+
+    @staticmethod
+    def backward(ctx, gU):
+        solver = ctx.solver
+        dts, als = ctx.sched
+        dts_h = dts.cpu().numpy()
+        als_h = als.cpu().numpy().reshape(-1, 2, 3).transpose(0, 2, 1)  # [n][stage][ax, ay]
+        lam = gU.detach().contiguous().clone()
+        nxt = torch.empty_like(lam)
+        nseg = len(ctx.ckpts)
+        for seg in range(nseg - 1, -1, -1):
+            s0 = seg * ctx.ckpt_every
+            k = min(ctx.ckpt_every, ctx.nsteps - s0)
+            states = [ctx.ckpts[seg]]
+            U = ctx.ckpts[seg].clone()
+            for i in range(k - 1):
+                solver.step(U, dts_h[s0 + i], alpha=als_h[s0 + i])
+                states.append(U.clone())
+            for i in range(k - 1, -1, -1):
+                solver.step_vjp(states[i], dts_h[s0 + i], als_h[s0 + i], lam, out=nxt)
+                lam, nxt = nxt, lam
+            del states
+        return lam, None, None, None
+
+
+def rollout(U0, solver, nsteps, ckpt_every=50):
+    """Differentiable nsteps-step rollout of U0 (float64, (4, ny, nx), on the solver's device)."""
+    return HydroRollout.apply(U0, solver, nsteps, ckpt_every)
+
+
+class HydroStep(torch.autograd.Function):
+    """One differentiable step with a given dt and (3, 2) LF speeds."""
+
+    @staticmethod
+    def forward(ctx, U, solver, dt, alpha):
+        out = U.detach().clone().contiguous()
+        solver.step(out, dt, alpha=alpha)
+        ctx.save_for_backward(U.detach().contiguous())
+        ctx.solver, ctx.dt, ctx.alpha = solver, dt, alpha
+        return out
+
+    @staticmethod
+    def backward(ctx, g):
+        (U,) = ctx.saved_tensors
+        return ctx.solver.step_vjp(U, ctx.dt, ctx.alpha, g.contiguous()), None, None, None

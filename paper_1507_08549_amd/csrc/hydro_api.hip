@@ -20,7 +20,7 @@ struct hydro_ctx {
   size_t n;              // cells
   double* U1;            // stage states
   double* U2;
-  double* X[4];          // adjoint scratch: recomputed stage states, stage adjoints
+  double* X[5];          // adjoint scratch: recomputed stage states, stage adjoints, partial sums
   hy::Ctl* ctl;          // device control block
   double* rec;           // device: alpha record of hydro_step ([6])
   double* partial;       // device: per-block partial sums
@@ -173,7 +173,7 @@ int hydro_create(const hydro_params* params, const double* gravity, void* stream
   const size_t bytes = 4 * c->n * sizeof(double);
   c->nsum = hy::sums_blocks(c->g);
   bool ok = hipMalloc(&c->U1, bytes) == hipSuccess && hipMalloc(&c->U2, bytes) == hipSuccess;
-  for (int k = 0; k < 4 && ok; ++k) ok = hipMalloc(&c->X[k], bytes) == hipSuccess;
+  for (int k = 0; k < 5 && ok; ++k) ok = hipMalloc(&c->X[k], bytes) == hipSuccess;
   ok = ok && hipMalloc(&c->ctl, sizeof(hy::Ctl)) == hipSuccess;
   ok = ok && hipMalloc(&c->rec, 8 * sizeof(double)) == hipSuccess;
   ok = ok && hipMalloc(&c->partial, (size_t)c->nsum * 8 * sizeof(double)) == hipSuccess;
@@ -328,6 +328,8 @@ int hydro_step_vjp(hydro_ctx* c, const double* U_n, double dt, const hydro_alpha
   v.dt = dt;
   v.fp32 = c->p.precision == HYDRO_FP32_BULK;
   v.ghost = c->ghost;
+  v.ghost_y_offset = 2 * 3 * 4 * (size_t)(c->p.nx > c->p.ny ? c->p.nx : c->p.ny);
+  v.Gp = c->X[4];
   // stage 3 (input R2): lam2 = 2/3 (lam3 + dt J^T lam3);  lam_prev = 1/3 lam3
   v.V = R2; v.lam = lam_next; v.b = kStageWeight[2]; v.ax = alpha->ax[2]; v.ay = alpha->ay[2];
   v.out = lam2; v.acc = nullptr; v.side = lam_prev; v.side_in = nullptr;

@@ -22,9 +22,13 @@ struct VjpArgs {
   const double* acc;
   double* side;
   const double* side_in;
-  double* ghost;  // scratch for the adjoint of ghost cells
+  double* ghost;  // scratch: adjoint of ghost cells, [2][3][ny][4] then [2][3][nx][4]
+  size_t ghost_y_offset;  // offset (doubles) of the y part in ghost
+  double* Gp;     // scratch state: partial J_L^T lam between the x and y passes
 };
 
 hipError_t launch_stage_vjp(const VjpArgs& a, hipStream_t s);
+hipError_t launch_stage_vjp_fp64(const VjpArgs& a, hipStream_t s);
+hipError_t launch_stage_vjp_fp32(const VjpArgs& a, hipStream_t s);
 
 }  // namespace hy

@@ -1,0 +1,385 @@
+// vjp_kernel.hpp -- the hand-written discrete adjoint of one Runge-Kutta stage.
+//
+// A stage is W = U0 + b ((V - U0) + dt L(V)) with
+//   L(V) = S(V) - (F^_{i+1/2} - F^_{i-1/2}) / dx - (G^_{j+1/2} - G^_{j-1/2}) / dy,
+//   F^ = W5(f+ left-biased) + W5(f- right-biased),  f+- = (F(U) +- alpha U) / 2
+// (Sect. 2.1, Eq. euler2D).  With the LF speeds alpha held at their recorded
+// values, its transpose applied to the adjoint lam of W is
+//   dJ/dV  = b (lam + dt J_L(V)^T lam),   dJ/dU0 = (1 - b) lam,
+// and J_L^T mu is assembled here from:
+//   * sources: (dS/dU)^T mu per cell (gravity; cylindrical geometric terms);
+//   * per face f: nu_c(f) = (mu_c(right cell) - mu_c(left cell)) / dx, the
+//     adjoint of F^_c(f) (faces on the domain boundary see mu = 0 outside);
+//   * per face and component: nu * dW5/dv for both reconstructions (the
+//     derivative runs through the nonlinear weights: beta-adjoints
+//     -2 omega_k (q_k - W) / (eps + beta_k)), gathered at every point the
+//     stencils touch (a gather, so no atomics and a fixed summation order);
+//   * per point: dU += A(U)^T (phi+ + phi-) / 2 + alpha (phi+ - phi-) / 2 with
+//     A = dF/dU the flux Jacobian;
+//   * ghost points: their adjoint belongs to the cell they were copied from
+//     (periodic image, mirror with the normal momentum negated, or the edge
+//     cell); it is written to a small side buffer and folded back by a
+//     separate tiny kernel in a fixed order.
+// The x and y parts run as two passes (x: sources + x fluxes into a partial
+// sum; y: y fluxes, then the stage combination), each staging a tile with a
+// five-cell halo along its own axis in LDS and processing one component at a
+// time to bound the LDS footprint.
+#pragma once
+
+#include "stage_kernel.hpp"
+#include "vjp.hpp"
+
+namespace hy {
+
+// nu * dW5/dv_m for the reconstruction W5(v0..v4) at the right face of v2.
+__device__ __forceinline__ void weno5_adj(const double v[5], double eps, double nu, double vb[5]) {
+  const double c1312 = 13.0 / 12.0;
+  const double d0 = v[0] - 2.0 * v[1] + v[2], e0 = v[0] - 4.0 * v[1] + 3.0 * v[2];
+  const double d1 = v[1] - 2.0 * v[2] + v[3], e1 = v[1] - v[3];
+  const double d2 = v[2] - 2.0 * v[3] + v[4], e2 = 3.0 * v[2] - 4.0 * v[3] + v[4];
+  const double E0 = eps + (c1312 * d0 * d0 + 0.25 * e0 * e0);
+  const double E1 = eps + (c1312 * d1 * d1 + 0.25 * e1 * e1);
+  const double E2 = eps + (c1312 * d2 * d2 + 0.25 * e2 * e2);
+  const double s0 = E0 * E0, s1 = E1 * E1, s2 = E2 * E2;
+  // weights over the common denominator; one division gives 1/sum(w) and 1/(E0 E1 E2)
+  const double w0 = s1 * s2, w1 = 6.0 * (s0 * s2), w2 = 3.0 * (s0 * s1);
+  const double sw = w0 + w1 + w2;
+  const double P = E0 * E1 * E2;
+  const double inv = 1.0 / (P * sw);
+  const double isw = P * inv, iP = sw * inv;
+  const double om0 = w0 * isw, om1 = w1 * isw, om2 = w2 * isw;
+  const double q0 = (2.0 * v[0] - 7.0 * v[1] + 11.0 * v[2]) * (1.0 / 6.0);
+  const double q1 = (-v[1] + 5.0 * v[2] + 2.0 * v[3]) * (1.0 / 6.0);
+  const double q2 = (2.0 * v[2] + 5.0 * v[3] - v[4]) * (1.0 / 6.0);
+  const double W = om0 * q0 + om1 * q1 + om2 * q2;
+  const double r0 = E1 * E2 * iP, r1 = E0 * E2 * iP, r2 = E0 * E1 * iP;  // 1 / E_k
+  const double bb0 = -2.0 * nu * om0 * (q0 - W) * r0;
+  const double bb1 = -2.0 * nu * om1 * (q1 - W) * r1;
+  const double bb2 = -2.0 * nu * om2 * (q2 - W) * r2;
+  const double c0 = nu * om0 * (1.0 / 6.0), c1 = nu * om1 * (1.0 / 6.0), c2 = nu * om2 * (1.0 / 6.0);
+  const double t0 = bb0 * (13.0 / 6.0) * d0, h0 = bb0 * 0.5 * e0;
+  const double t1 = bb1 * (13.0 / 6.0) * d1, h1 = bb1 * 0.5 * e1;
+  const double t2 = bb2 * (13.0 / 6.0) * d2, h2 = bb2 * 0.5 * e2;
+  vb[0] = 2.0 * c0 + t0 + h0;
+  vb[1] = -7.0 * c0 - c1 - 2.0 * t0 - 4.0 * h0 + t1 + h1;
+  vb[2] = 11.0 * c0 + 5.0 * c1 + 2.0 * c2 + t0 + 3.0 * h0 - 2.0 * t1 + t2 + 3.0 * h2;
+  vb[3] = 2.0 * c1 + 5.0 * c2 + t1 - h1 - 2.0 * t2 - 4.0 * h2;
+  vb[4] = -c2 + t2 + h2;
+}
+
+// Single precision: textbook weights with hardware reciprocals.
+__device__ __forceinline__ void weno5_adj(const float v[5], float eps, float nu, float vb[5]) {
+  const float c1312 = 13.0f / 12.0f;
+  const float d0 = v[0] - 2.0f * v[1] + v[2], e0 = v[0] - 4.0f * v[1] + 3.0f * v[2];
+  const float d1 = v[1] - 2.0f * v[2] + v[3], e1 = v[1] - v[3];
+  const float d2 = v[2] - 2.0f * v[3] + v[4], e2 = 3.0f * v[2] - 4.0f * v[3] + v[4];
+  const float r0 = rcpf(eps + (c1312 * d0 * d0 + 0.25f * e0 * e0));
+  const float r1 = rcpf(eps + (c1312 * d1 * d1 + 0.25f * e1 * e1));
+  const float r2 = rcpf(eps + (c1312 * d2 * d2 + 0.25f * e2 * e2));
+  const float a0 = 0.1f * r0 * r0, a1 = 0.6f * r1 * r1, a2 = 0.3f * r2 * r2;
+  const float ia = rcpf(a0 + a1 + a2);
+  const float om0 = a0 * ia, om1 = a1 * ia, om2 = a2 * ia;
+  const float q0 = (2.0f * v[0] - 7.0f * v[1] + 11.0f * v[2]) * (1.0f / 6.0f);
+  const float q1 = (-v[1] + 5.0f * v[2] + 2.0f * v[3]) * (1.0f / 6.0f);
+  const float q2 = (2.0f * v[2] + 5.0f * v[3] - v[4]) * (1.0f / 6.0f);
+  const float W = om0 * q0 + om1 * q1 + om2 * q2;
+  const float bb0 = -2.0f * nu * om0 * (q0 - W) * r0;
+  const float bb1 = -2.0f * nu * om1 * (q1 - W) * r1;
+  const float bb2 = -2.0f * nu * om2 * (q2 - W) * r2;
+  const float c0 = nu * om0 * (1.0f / 6.0f), c1 = nu * om1 * (1.0f / 6.0f), c2 = nu * om2 * (1.0f / 6.0f);
+  const float t0 = bb0 * (13.0f / 6.0f) * d0, h0 = bb0 * 0.5f * e0;
+  const float t1 = bb1 * (13.0f / 6.0f) * d1, h1 = bb1 * 0.5f * e1;
+  const float t2 = bb2 * (13.0f / 6.0f) * d2, h2 = bb2 * 0.5f * e2;
+  vb[0] = 2.0f * c0 + t0 + h0;
+  vb[1] = -7.0f * c0 - c1 - 2.0f * t0 - 4.0f * h0 + t1 + h1;
+  vb[2] = 11.0f * c0 + 5.0f * c1 + 2.0f * c2 + t0 + 3.0f * h0 - 2.0f * t1 + t2 + 3.0f * h2;
+  vb[3] = 2.0f * c1 + 5.0f * c2 + t1 - h1 - 2.0f * t2 - 4.0f * h2;
+  vb[4] = -c2 + t2 + h2;
+}
+
+// Quantities of a point that the flux-Jacobian rows need.
+template <typename R> struct JacPt { R u, v, H, hq; };  // hq = (gamma-1) |v|^2 / 2
+
+template <typename R>
+__device__ __forceinline__ JacPt<R> jac_point(R r, R mx, R my, R E, R gamma, R gm1) {
+  const Prim<R> w = prim(r, mx, my, E, gamma, gm1);
+  JacPt<R> j;
+  j.u = w.u;
+  j.v = w.v;
+  j.H = (E + w.p) / r;
+  j.hq = R(0.5) * gm1 * (w.u * w.u + w.v * w.v);
+  return j;
+}
+
+// dU += A_c^T psi / 2 + alpha e_c delta / 2 for component c of direction DIR
+// (psi = phi+ + phi-, delta = phi+ - phi-), A = dF/dU of that direction.
+template <int DIR, typename R>
+__device__ __forceinline__ void jacT_row(int c, const JacPt<R>& j, R gamma, R gm1, R alpha, R psi,
+                                         R delta, R dU[4]) {
+  const R h = R(0.5) * psi;
+  const R u = DIR == 0 ? j.u : j.v;  // normal velocity
+  const R t = DIR == 0 ? j.v : j.u;  // tangential velocity
+  const int cn = DIR == 0 ? 1 : 2;   // normal-momentum component
+  const int ct = DIR == 0 ? 2 : 1;   // tangential-momentum component
+  if (c == 0) {
+    dU[cn] += h;
+  } else if (c == cn) {
+    dU[0] += h * (j.hq - u * u);
+    dU[cn] += h * ((R(3) - gamma) * u);
+    dU[ct] += h * (-gm1 * t);
+    dU[3] += h * gm1;
+  } else if (c == ct) {
+    dU[0] += h * (-u * t);
+    dU[cn] += h * t;
+    dU[ct] += h * u;
+  } else {
+    dU[0] += h * (u * (j.hq - j.H));
+    dU[cn] += h * (j.H - gm1 * u * u);
+    dU[ct] += h * (-gm1 * u * t);
+    dU[3] += h * (gamma * u);
+  }
+  dU[c] += R(0.5) * alpha * delta;
+}
+
+struct VjpPass {
+  VjpArgs a;
+  double* Gp;      // partial J_L^T mu (x pass writes, y pass reads)
+  int finalize;    // this pass writes out / side
+  double* ghost;   // ghost adjoints of this pass's axis: [2][3][n_across][4]
+};
+
+// One pass (DIR 0: x, with the source adjoint; DIR 1: y) over a tile of NA
+// cells along the axis and NC lines across it.
+template <typename R, int DIR, int NA, int NC>
+__global__ __launch_bounds__(256) void vjp_pass_kernel(VjpPass P) {
+  constexpr int NT = 256;
+  static_assert(NA * NC == NT, "one tile cell per work item");
+  constexpr int LP = NA + 10;  // points with a five-cell halo
+  constexpr int LM = NA + 6;   // adjoint values with a three-cell halo
+  constexpr int LF = NA + 5;   // faces a0-2 .. a0+NA+2
+  __shared__ R sU[4][NC][LP];
+  __shared__ R sF[8][NC][LP];
+  __shared__ R sM[4][NC][LM];
+  __shared__ R sD[10][NC][LF];
+
+  const VjpArgs& a = P.a;
+  const Geom& g = a.g;
+  const int tid = threadIdx.x;
+  const int na = DIR == 0 ? g.nx : g.ny;  // cells along the pass axis
+  const int nc = DIR == 0 ? g.ny : g.nx;  // lines across it
+  const int bc_lo = DIR == 0 ? g.bc[0] : g.bc[2];
+  const int bc_hi = DIR == 0 ? g.bc[1] : g.bc[3];
+  const int cn = DIR == 0 ? 1 : 2;
+  const int nta = (na + NA - 1) / NA;
+  const int a0 = (blockIdx.x % nta) * NA;
+  const int b0 = (blockIdx.x / nta) * NC;
+  const size_t n = (size_t)g.nx * g.ny;
+  const R gamma = (R)g.gamma, gm1 = (R)g.gm1, eps = (R)g.eps;
+  const R alpha = (R)(DIR == 0 ? a.ax : a.ay);
+  const R id = (R)(DIR == 0 ? g.idx : g.idy);
+
+  auto gidx = [&](int along, int across) -> size_t {
+    return DIR == 0 ? (size_t)across * g.nx + along : (size_t)along * g.nx + across;
+  };
+
+  // ---- stage V (with ghosts along the axis) and mu (zero outside the domain)
+  for (int k = tid; k < NC * LP; k += NT) {
+    const int b = DIR == 0 ? k / LP : k % NC;
+    const int la = DIR == 0 ? k % LP : k / NC;
+    const int B = b0 + b < nc ? b0 + b : nc - 1;
+    bool flip;
+    const int s = map_index(a0 - 5 + la, na, bc_lo, bc_hi, flip);
+    const size_t q = gidx(s, B);
+    R u4[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) u4[c] = (R)a.V[c * n + q];
+    if (flip) u4[cn] = -u4[cn];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) sU[c][b][la] = u4[c];
+    R fp[4], fm[4];
+    split_flux<DIR>(u4, gamma, gm1, alpha, fp, fm);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      sF[c][b][la] = fp[c];
+      sF[4 + c][b][la] = fm[c];
+    }
+  }
+  for (int k = tid; k < NC * LM; k += NT) {
+    const int b = DIR == 0 ? k / LM : k % NC;
+    const int lm = DIR == 0 ? k % LM : k / NC;
+    const int A = a0 - 3 + lm;
+    const bool in = A >= 0 && A < na && b0 + b < nc;
+    const size_t q = in ? gidx(A, b0 + b) : 0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) sM[c][b][lm] = in ? (R)a.lam[c * n + q] : R(0);
+  }
+  __syncthreads();
+
+  // ---- the points this work item owns: one tile cell, and possibly a ghost
+  const int pb0 = tid / NA, pa0 = tid % NA;  // tile cell
+  const bool own_lo = a0 == 0;
+  const bool own_hi = a0 <= na - 1 && na - 1 < a0 + NA;
+  const int ng = (own_lo ? 3 * NC : 0) + (own_hi ? 3 * NC : 0);
+  int gk = -1000, gb = 0;  // ghost point along index and line
+  if (tid < ng) {
+    int t = tid;
+    if (own_lo && t < 3 * NC) {
+      gb = t / 3;
+      gk = -1 - (t % 3);
+    } else {
+      if (own_lo) t -= 3 * NC;
+      gb = t / 3;
+      gk = na + (t % 3);
+    }
+  }
+  const bool cell_act = a0 + pa0 < na && b0 + pb0 < nc;
+  const bool ghost_act = tid < ng && b0 + gb < nc;
+  R dU[4] = {R(0), R(0), R(0), R(0)};
+  R dG[4] = {R(0), R(0), R(0), R(0)};
+  JacPt<R> jc, jg;
+  {
+    const int la = pa0 + 5;
+    jc = jac_point<R>(sU[0][pb0][la], sU[1][pb0][la], sU[2][pb0][la], sU[3][pb0][la], gamma, gm1);
+    const int lg = ghost_act ? gk - a0 + 5 : 5;
+    const int bb = ghost_act ? gb : 0;
+    jg = jac_point<R>(sU[0][bb][lg], sU[1][bb][lg], sU[2][bb][lg], sU[3][bb][lg], gamma, gm1);
+  }
+
+  for (int c = 0; c < 4; ++c) {
+    // per face: nu * dW/dv of both reconstructions of component c
+    for (int t = tid; t < NC * LF; t += NT) {
+      const int b = t / LF, lf = t % LF;
+      const int f = a0 - 2 + lf;  // global face index (face f: between cells f-1 and f)
+      const bool face_in = f >= 0 && f <= na && b0 + b < nc;
+      // local mu index of cell f is f - (a0 - 3) = lf + 1
+      const R nu = face_in ? (sM[c][b][lf + 1] - sM[c][b][lf]) * id : R(0);
+      R vp[5], vm[5], gp[5], gm[5];
+#pragma unroll
+      for (int m = 0; m < 5; ++m) {
+        vp[m] = sF[c][b][lf + m];
+        vm[m] = sF[4 + c][b][lf + 5 - m];
+      }
+      weno5_adj(vp, eps, nu, gp);
+      weno5_adj(vm, eps, nu, gm);
+#pragma unroll
+      for (int m = 0; m < 5; ++m) {
+        sD[m][b][lf] = gp[m];
+        sD[5 + m][b][lf] = gm[m];
+      }
+    }
+    __syncthreads();
+    // gather at the owned points: phi+(k) = sum_m D+_m(f = k+3-m), phi-(k) = sum_m D-_m(f = k-2+m)
+    auto gather = [&](int k, int b, R& php, R& phm) {
+      php = R(0);
+      phm = R(0);
+#pragma unroll
+      for (int m = 0; m < 5; ++m) {
+        const int lf1 = k + 3 - m - (a0 - 2);
+        if (lf1 >= 0 && lf1 < LF) php += sD[m][b][lf1];
+        const int lf2 = k - 2 + m - (a0 - 2);
+        if (lf2 >= 0 && lf2 < LF) phm += sD[5 + m][b][lf2];
+      }
+    };
+    {
+      R php, phm;
+      gather(a0 + pa0, pb0, php, phm);
+      jacT_row<DIR, R>(c, jc, gamma, gm1, alpha, php + phm, php - phm, dU);
+      if (ghost_act) {
+        gather(gk, gb, php, phm);
+        jacT_row<DIR, R>(c, jg, gamma, gm1, alpha, php + phm, php - phm, dG);
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- ghost adjoints to the side buffer (folded onto their source cells later)
+  if (ghost_act) {
+    const int side = gk < 0 ? 0 : 1;
+    const int layer = gk < 0 ? -gk - 1 : gk - na;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      P.ghost[(((size_t)side * 3 + layer) * nc + (b0 + gb)) * 4 + c] = (double)dG[c];
+  }
+  if (!cell_act) return;
+
+  const size_t q = gidx(a0 + pa0, b0 + pb0);
+  double G[4];
+  if (DIR == 0) {
+    // sources of Eq. euler2D, transposed
+    const int la = pa0 + 5;
+    const R r = sU[0][pb0][la], mx = sU[1][pb0][la], my = sU[2][pb0][la], E = sU[3][pb0][la];
+    const R m0 = sM[0][pb0][pa0 + 3], m1 = sM[1][pb0][pa0 + 3], m2 = sM[2][pb0][pa0 + 3],
+            m3 = sM[3][pb0][pa0 + 3];
+    const R gxv = g.grav ? (R)g.grav[q] : (R)g.gx;
+    const R gyv = g.grav ? (R)g.grav[n + q] : (R)g.gy;
+    R S[4];
+    S[0] = gxv * m1 + gyv * m2;
+    S[1] = gxv * m3;
+    S[2] = gyv * m3;
+    S[3] = R(0);
+    if (g.cyl) {
+      const double ri = g.xlo + ((double)(a0 + pa0) + 0.5) * g.dx;
+      const R ir = (R)(1.0 / ri);
+      const R u = jc.u, v = jc.v;
+      const R Eo = E / r;  // E / rho
+      // d/dU of (m_r, m_r u, m_z u, (E + p) u), transposed onto mu, times -1/r
+      S[0] -= ir * (-u * u * m1 - u * v * m2 + u * (R(2) * jc.hq - gamma * Eo) * m3);
+      S[1] -= ir * (m0 + R(2) * u * m1 + v * m2 + (gamma * Eo - jc.hq - gm1 * u * u) * m3);
+      S[2] -= ir * (u * m2 - gm1 * u * v * m3);
+      S[3] -= ir * (gamma * u * m3);
+      (void)mx;
+      (void)my;
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) G[c] = (double)(S[c] + dU[c]);
+  } else {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) G[c] = P.Gp[c * n + q] + (double)dU[c];
+  }
+  if (!P.finalize) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) P.Gp[c * n + q] = G[c];
+    return;
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const double l = a.lam[c * n + q];
+    double o = a.b * __builtin_fma(a.dt, G[c], l);
+    if (a.acc) o += a.acc[c * n + q];
+    if (a.side) {
+      const double s = (1.0 - a.b) * l;
+      a.side[c * n + q] = a.side_in ? a.side_in[c * n + q] + s : s;
+    }
+    a.out[c * n + q] = o;
+  }
+}
+
+// Adds scale * (adjoint of each ghost point) onto the cell it was copied from,
+// one line per work item, in a fixed order (deterministic, no atomics).
+// (Templated on the pass precision only so each instantiating unit owns a copy.)
+template <typename R>
+__global__ void vjp_fold_kernel(Geom g, int dir, const double* ghost, double* out, double scale) {
+  const int na = dir == 0 ? g.nx : g.ny;
+  const int nc = dir == 0 ? g.ny : g.nx;
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nc) return;
+  const int lo = dir == 0 ? g.bc[0] : g.bc[2];
+  const int hi = dir == 0 ? g.bc[1] : g.bc[3];
+  const int cn = dir == 0 ? 1 : 2;
+  const size_t n = (size_t)g.nx * g.ny;
+  for (int side = 0; side < 2; ++side)
+    for (int layer = 0; layer < 3; ++layer) {
+      const int k = side == 0 ? -1 - layer : na + layer;
+      bool flip;
+      const int s = map_index(k, na, lo, hi, flip);
+      const size_t q = dir == 0 ? (size_t)b * g.nx + s : (size_t)s * g.nx + b;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        double v = ghost[(((size_t)side * 3 + layer) * nc + b) * 4 + c];
+        if (flip && c == cn) v = -v;
+        out[c * n + q] += scale * v;
+      }
+    }
+}
+
+}  // namespace hy

@@ -211,6 +211,19 @@ class Solver:
             als = als[:k].reshape(k, 2, 3).transpose(1, 2)
         return k, tt.value, dts, als
 
+    def run_into(self, U, nsteps, dt_rec, alpha_rec, t_end=0.0, t0=0.0):
+        """hydro_run recording into caller-provided device tensors dt_rec (nsteps,)
+        and alpha_rec (nsteps, 6) (ax[0..2], ay[0..2] per step).  Returns steps taken."""
+        t = self.torch
+        for name, x, shape in (("dt_rec", dt_rec, (nsteps,)), ("alpha_rec", alpha_rec, (nsteps, 6))):
+            if (not isinstance(x, t.Tensor) or x.dtype != t.float64 or x.device != self.device
+                    or tuple(x.shape) != shape or not x.is_contiguous()):
+                raise ValueError(f"{name} must be a contiguous float64 {shape} tensor on {self.device}")
+        tt = ctypes.c_double(float(t0))
+        rc = self._lib.hydro_run(self._h, self._state(U), int(nsteps), float(t_end), ctypes.byref(tt),
+                                 dt_rec.data_ptr(), alpha_rec.data_ptr())
+        return self._check(rc, "hydro_run")
+
     def rhs(self, V, ax, ay, out=None):
         L = self.new_state() if out is None else out
         self._check(self._lib.hydro_rhs(self._h, self._state(V), float(ax), float(ay),

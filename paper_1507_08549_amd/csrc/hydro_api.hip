@@ -25,6 +25,7 @@ struct hydro_ctx {
   double* rec;           // device: alpha record of hydro_step ([6])
   double* partial;       // device: per-block partial sums
   double* sum_out;       // device: [4]
+  double* apart;         // device: partial maxima of the LF/CFL reduction ([256][4])
   double* ghost;         // device: adjoint of ghost cells ([2][3][max(nx, ny)][4] per axis)
   int nsum;
   hy::Ctl* h_ctl;        // pinned host staging
@@ -129,7 +130,7 @@ hy::StageArgs stage_args(const hydro_ctx* c, double* U, int s) {
 }
 
 int read_flag(hydro_ctx* c, bool clear) {
-  HY_CHECK(hipMemcpyAsync(c->h_ctl, c->ctl, sizeof(hy::Ctl), hipMemcpyDeviceToHost, c->stream));
+  HY_CHECK(hipMemcpyAsync(c->h_ctl, c->ctl, hy::kCtlHeader, hipMemcpyDeviceToHost, c->stream));
   HY_CHECK(hipStreamSynchronize(c->stream));
   const int f = c->h_ctl->flag;
   if (f && clear) {
@@ -149,6 +150,7 @@ void free_ctx(hydro_ctx* c) {
   (void)hipFree(c->partial);
   (void)hipFree(c->sum_out);
   (void)hipFree(c->ghost);
+  (void)hipFree(c->apart);
   (void)hipHostFree(c->h_ctl);
   (void)hipHostFree(c->h_buf);
   delete c;
@@ -179,6 +181,7 @@ int hydro_create(const hydro_params* params, const double* gravity, void* stream
   ok = ok && hipMalloc(&c->partial, (size_t)c->nsum * 8 * sizeof(double)) == hipSuccess;
   ok = ok && hipMalloc(&c->sum_out, 4 * sizeof(double)) == hipSuccess;
   const size_t nmax = (size_t)(params->nx > params->ny ? params->nx : params->ny);
+  ok = ok && hipMalloc(&c->apart, 256 * 4 * sizeof(double)) == hipSuccess;
   ok = ok && hipMalloc(&c->ghost, 2 * 2 * 3 * nmax * 4 * sizeof(double)) == hipSuccess;
   ok = ok && hipHostMalloc((void**)&c->h_ctl, sizeof(hy::Ctl), hipHostMallocDefault) == hipSuccess;
   ok = ok && hipHostMalloc((void**)&c->h_buf, 8 * sizeof(double), hipHostMallocDefault) == hipSuccess;
@@ -208,11 +211,13 @@ int hydro_cfl(hydro_ctx* c, const double* U, double* dt_host) {
   if (!c || !U || !dt_host) return HYDRO_E_INVALID;
   DeviceGuard dg(c->device);
   if (!dg.ok) return HYDRO_E_DEVICE;
-  HY_CHECK(hy::launch_clear_slots(c->ctl, c->stream));
-  HY_CHECK(hy::launch_alpha_reduce(c->g, U, c->ctl, 0, c->stream));
+  HY_CHECK(hy::launch_alpha_reduce(c->g, U, c->ctl, 0, c->apart, c->stream));
   int rc = read_flag(c, false);
   if (rc) return rc;
-  const double smax = *reinterpret_cast<const double*>(&c->h_ctl->slot[0][2]);
+  HY_CHECK(hipMemcpyAsync(c->h_buf, &c->ctl->slot[0][0][0], 3 * sizeof(double), hipMemcpyDeviceToHost,
+                          c->stream));
+  HY_CHECK(hipStreamSynchronize(c->stream));
+  const double smax = c->h_buf[2];
   *dt_host = c->g.cfl_dmin / smax;
   return HYDRO_OK;
 }
@@ -222,10 +227,8 @@ int hydro_step(hydro_ctx* c, double* U, double dt, const hydro_alpha* alpha_in,
   if (!c || !U || !(dt >= 0.0)) return HYDRO_E_INVALID;
   DeviceGuard dg(c->device);
   if (!dg.ok) return HYDRO_E_DEVICE;
-  if (!alpha_in) {
-    HY_CHECK(hy::launch_clear_slots(c->ctl, c->stream));
-    HY_CHECK(hy::launch_alpha_reduce(c->g, U, c->ctl, 0, c->stream));
-  }
+  if (!alpha_in) HY_CHECK(hy::launch_alpha_reduce(c->g, U, c->ctl, 0, c->apart, c->stream));
+  else HY_CHECK(hy::launch_clear_slots(c->ctl, c->stream));
   for (int s = 0; s < 3; ++s) {
     hy::StageArgs a = stage_args(c, U, s);
     a.dt_mode = 0;
@@ -257,8 +260,7 @@ int hydro_run(hydro_ctx* c, double* U, int32_t nsteps, double t_end, double* t_i
   const double t0 = t_io ? *t_io : 0.0;
   hipLaunchKernelGGL(set_ctl_kernel, dim3(1), dim3(64), 0, c->stream, c->ctl, t0);
   HY_CHECK(hipGetLastError());
-  HY_CHECK(hy::launch_clear_slots(c->ctl, c->stream));
-  HY_CHECK(hy::launch_alpha_reduce(c->g, U, c->ctl, 0, c->stream));
+  HY_CHECK(hy::launch_alpha_reduce(c->g, U, c->ctl, 0, c->apart, c->stream));
   for (int k = 0; k < nsteps; ++k) {
     for (int s = 0; s < 3; ++s) {
       hy::StageArgs a = stage_args(c, U, s);

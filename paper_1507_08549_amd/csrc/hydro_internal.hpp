@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 namespace hy {
@@ -37,15 +38,22 @@ struct Geom {
 // ring over the Runge-Kutta stages: stage k reads slot k % 3 (its input's
 // speeds), accumulates its output's speeds into slot (k + 1) % 3 and clears
 // slot (k + 2) % 3 for the stage after it.
+// Each slot is split into NSUB sub-slots on separate 128-byte lines:
+// workgroup b merges into sub-slot b % NSUB, so the device-scope atomics of
+// different workgroups do not queue on one address; a reader takes the max
+// over the sub-slots (one wavefront, NSUB = 64 lanes).
+constexpr int NSUB = 64;
 struct Ctl {
-  unsigned long long slot[3][4];
   double dt;     // time step of the current step (device-computed mode)
   double t;      // time reached
   int active;    // current step is taken (t < t_end)
   int steps;     // steps taken by hydro_run
   int flag;      // sticky: a stage produced rho <= 0 or p <= 0
-  int pad;
+  int pad[9];
+  unsigned long long slot[3][NSUB][16];
 };
+constexpr size_t kCtlHeader = 64;  // bytes before slot[][][]: what the host reads back
+static_assert(offsetof(Ctl, slot) == kCtlHeader, "control header layout");
 
 struct StageArgs {
   Geom g;
@@ -69,7 +77,10 @@ struct StageArgs {
 hipError_t launch_stage_fp64(const StageArgs& a, hipStream_t s);
 hipError_t launch_stage_fp32(const StageArgs& a, hipStream_t s);
 hipError_t launch_clear_slots(Ctl* ctl, hipStream_t s);
-hipError_t launch_alpha_reduce(const Geom& g, const double* U, Ctl* ctl, int slot, hipStream_t s);
+// Maxima of a state into ctl->slot[slot]; clears the other two slots.
+// partial: scratch of 4 * 256 doubles.
+hipError_t launch_alpha_reduce(const Geom& g, const double* U, Ctl* ctl, int slot, double* partial,
+                               hipStream_t s);
 hipError_t launch_sums(const Geom& g, const double* U, double* partial, int nblocks, double* out,
                        hipStream_t s);
 int sums_blocks(const Geom& g);

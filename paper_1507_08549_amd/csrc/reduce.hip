@@ -7,8 +7,10 @@
 namespace hy {
 
 __global__ void clear_slots_kernel(Ctl* ctl) {
-  const int k = threadIdx.x;
-  if (k < 12) ctl->slot[k / 4][k % 4] = 0ull;
+  const int t = threadIdx.x;  // one sub-slot per work item
+  if (t >= NSUB) return;
+  for (int s = 0; s < 3; ++s)
+    for (int k = 0; k < 3; ++k) ctl->slot[s][t][k] = 0ull;
 }
 
 hipError_t launch_clear_slots(Ctl* ctl, hipStream_t s) {
@@ -16,9 +18,14 @@ hipError_t launch_clear_slots(Ctl* ctl, hipStream_t s) {
   return hipGetLastError();
 }
 
-// max over cells of |u|+c, |v|+c and c+(|u|+|v|) into ctl->slot[slot]; sets the
-// sticky flag if rho <= 0, p <= 0 or c is not finite anywhere.
-__global__ __launch_bounds__(256) void alpha_reduce_kernel(Geom g, const double* U, Ctl* ctl, int slot) {
+// max over cells of |u|+c, |v|+c and c+(|u|+|v|): per-block maxima into
+// partial[b][0..2] (partial[b][3] = 1 if rho <= 0, p <= 0 or c is not finite
+// in the block), then one block merges them (no atomics).
+constexpr int RED_THREADS = 256;
+constexpr int RED_MAX_BLOCKS = 256;
+
+__global__ __launch_bounds__(RED_THREADS) void alpha_partial_kernel(Geom g, const double* U,
+                                                                    double* partial) {
   const size_t n = (size_t)g.nx * g.ny;
   double amax = 0.0, bmax = 0.0, smax = 0.0;
   bool bad = false;
@@ -37,7 +44,7 @@ __global__ __launch_bounds__(256) void alpha_reduce_kernel(Geom g, const double*
     bmax = __builtin_fmax(bmax, __shfl_xor(bmax, off));
     smax = __builtin_fmax(smax, __shfl_xor(smax, off));
   }
-  __shared__ double red[4][3];
+  __shared__ double red[RED_THREADS / 64][3];
   const int wave = threadIdx.x / 64;
   if ((threadIdx.x & 63) == 0) {
     red[wave][0] = amax;
@@ -46,23 +53,53 @@ __global__ __launch_bounds__(256) void alpha_reduce_kernel(Geom g, const double*
   }
   const int anybad = __syncthreads_or(bad ? 1 : 0);
   if (threadIdx.x == 0) {
-    for (int k = 1; k < 4; ++k) {
+    for (int k = 1; k < RED_THREADS / 64; ++k) {
       amax = __builtin_fmax(amax, red[k][0]);
       bmax = __builtin_fmax(bmax, red[k][1]);
       smax = __builtin_fmax(smax, red[k][2]);
     }
-    atomicMax(&ctl->slot[slot][0], as_bits(amax));
-    atomicMax(&ctl->slot[slot][1], as_bits(bmax));
-    atomicMax(&ctl->slot[slot][2], as_bits(smax));
-    if (anybad) atomicOr(&ctl->flag, 1);
+    partial[blockIdx.x * 4 + 0] = amax;
+    partial[blockIdx.x * 4 + 1] = bmax;
+    partial[blockIdx.x * 4 + 2] = smax;
+    partial[blockIdx.x * 4 + 3] = anybad ? 1.0 : 0.0;
   }
 }
 
-hipError_t launch_alpha_reduce(const Geom& g, const double* U, Ctl* ctl, int slot, hipStream_t s) {
+// Merge the partial maxima into ring slot `slot` (sub-slot 0 holds the max,
+// the other sub-slots zero) and clear the two other slots.  One wavefront.
+__global__ void alpha_final_kernel(const double* partial, int nb, Ctl* ctl, int slot) {
+  const int t = threadIdx.x;
+  double m[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = t; b < nb; b += 64)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) m[k] = __builtin_fmax(m[k], partial[b * 4 + k]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) m[k] = __builtin_fmax(m[k], __shfl_xor(m[k], off));
+  if (t < NSUB) {
+    for (int k = 0; k < 3; ++k) {
+      ctl->slot[slot][t][k] = t == 0 ? as_bits(m[k]) : 0ull;
+      ctl->slot[(slot + 1) % 3][t][k] = 0ull;
+      ctl->slot[(slot + 2) % 3][t][k] = 0ull;
+    }
+  }
+  if (t == 0 && m[3] != 0.0) atomicOr(&ctl->flag, 1);
+}
+
+int alpha_blocks(const Geom& g) {
   const size_t n = (size_t)g.nx * g.ny;
-  size_t nb = (n + 255) / 256;
-  if (nb > 2048) nb = 2048;
-  hipLaunchKernelGGL(alpha_reduce_kernel, dim3((unsigned)nb), dim3(256), 0, s, g, U, ctl, slot);
+  size_t nb = (n + RED_THREADS * 8 - 1) / (RED_THREADS * 8);
+  if (nb < 1) nb = 1;
+  if (nb > RED_MAX_BLOCKS) nb = RED_MAX_BLOCKS;
+  return (int)nb;
+}
+
+hipError_t launch_alpha_reduce(const Geom& g, const double* U, Ctl* ctl, int slot, double* partial,
+                               hipStream_t s) {
+  const int nb = alpha_blocks(g);
+  hipLaunchKernelGGL(alpha_partial_kernel, dim3(nb), dim3(RED_THREADS), 0, s, g, U, partial);
+  hipLaunchKernelGGL(alpha_final_kernel, dim3(1), dim3(64), 0, s, (const double*)partial, nb, ctl, slot);
   return hipGetLastError();
 }
 

@@ -166,6 +166,30 @@ __device__ __forceinline__ void split_flux(const R U[4], R gamma, R gm1, R alpha
   }
 }
 
+// Max over the NSUB sub-slots of ring slot s, by wavefront 0, broadcast to the
+// block through LDS.  Every work item of the block must call it.
+__device__ __forceinline__ void read_slot(const Ctl* ctl, int s, double out[3], double* sh) {
+  if (threadIdx.x < NSUB) {
+    const unsigned long long* p = ctl->slot[s][threadIdx.x];
+    double m0 = as_double(p[0]), m1 = as_double(p[1]), m2 = as_double(p[2]);
+#pragma unroll
+    for (int off = NSUB / 2; off > 0; off >>= 1) {
+      m0 = __builtin_fmax(m0, __shfl_xor(m0, off));
+      m1 = __builtin_fmax(m1, __shfl_xor(m1, off));
+      m2 = __builtin_fmax(m2, __shfl_xor(m2, off));
+    }
+    if (threadIdx.x == 0) {
+      sh[0] = m0;
+      sh[1] = m1;
+      sh[2] = m2;
+    }
+  }
+  __syncthreads();
+  out[0] = sh[0];
+  out[1] = sh[1];
+  out[2] = sh[2];
+}
+
 // Block index -> tile index.  Workgroups are dispatched round-robin over the
 // 8 XCDs; remapping so that each XCD receives a contiguous run of tiles
 // (whole tile rows) keeps neighbouring tiles' shared halo rows in the same L2.
@@ -189,15 +213,20 @@ __global__ __launch_bounds__(TX* TY) void stage_kernel(StageArgs a) {
   constexpr int NW = (NT + 63) / 64;
   static_assert(NT % 64 == 0, "whole wavefronts");
 
-  __shared__ R sU[4][TYP * TXP];
+  static_assert(8 * NP >= 4 * NF, "face values fit in the split-flux storage");
   __shared__ R sF[8][NP];
-  __shared__ R sFh[4][NF];
   __shared__ double sRed[NW][3];
 
   const Geom& g = a.g;
   Ctl* ctl = a.ctl;
   const int tid = threadIdx.x;
   const bool lead = (blockIdx.x == 0 && tid == 0);
+
+  // ---- speeds of this stage's input (LF alphas; CFL speed for stage 0)
+  __shared__ double sSlot[3];
+  double sp[3] = {a.fax, a.fay, 0.0};
+  const bool use_slot = !a.rhs_only && (!a.frozen || a.dt_mode == 1);
+  if (use_slot) read_slot(ctl, a.stage, sp, sSlot);
 
   // ---- time step and whether this step is taken
   double dt = a.dt_host;
@@ -206,8 +235,7 @@ __global__ __launch_bounds__(TX* TY) void stage_kernel(StageArgs a) {
     if (a.stage == 0) {
       double t = ctl->t;
       active = !(a.t_end > 0.0) || (t < a.t_end);
-      double smax = as_double(ctl->slot[0][2]);
-      dt = g.cfl_dmin / smax;
+      dt = g.cfl_dmin / sp[2];
       if (a.t_end > 0.0 && t + dt > a.t_end) dt = a.t_end - t;
       if (lead) {
         ctl->active = active ? 1 : 0;
@@ -221,19 +249,17 @@ __global__ __launch_bounds__(TX* TY) void stage_kernel(StageArgs a) {
   }
   if (!active) return;
 
-  // ---- LF speeds of this stage's input
-  double ax, ay;
-  if (a.frozen || a.rhs_only) {
-    ax = a.fax;
-    ay = a.fay;
-  } else {
-    ax = as_double(ctl->slot[a.stage][0]);
-    ay = as_double(ctl->slot[a.stage][1]);
+  const double ax = a.frozen || a.rhs_only ? a.fax : sp[0];
+  const double ay = a.frozen || a.rhs_only ? a.fay : sp[1];
+  if (!a.rhs_only && blockIdx.x == 0 && tid < NSUB) {
+    // clear the slot two stages ahead (one sub-slot per lane)
+    unsigned long long* z = ctl->slot[(a.stage + 2) % 3][tid];
+    z[0] = 0ull;
+    z[1] = 0ull;
+    z[2] = 0ull;
   }
   if (lead && !a.rhs_only) {
     const int s = a.stage;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) ctl->slot[(s + 2) % 3][k] = 0ull;
     if (a.alpha_rec) {
       a.alpha_rec[s] = ax;
       a.alpha_rec[3 + s] = ay;
@@ -251,34 +277,32 @@ __global__ __launch_bounds__(TX* TY) void stage_kernel(StageArgs a) {
   const size_t n = (size_t)g.nx * g.ny;
   const R gamma = (R)g.gamma, gm1 = (R)g.gm1, eps = (R)g.eps;
 
-  // ---- 1. stage the tile and its halo cross in LDS (boundary conditions here)
-  for (int k = tid; k < TYP * TXP; k += NT) {
-    const int ly = k / TXP, lx = k - ly * TXP;
-    const bool inx = lx >= NG && lx < NG + TX;
-    const bool iny = ly >= GY && ly < GY + TY;
-    if (!inx && !iny) continue;  // corners: not on any stencil
+  // State of a (possibly ghost) point: boundary conditions applied on load.
+  auto load_point = [&](int I, int J, R U[4]) {
     bool fx, fy = false;
-    const int si = map_index(i0 + lx - NG, g.nx, g.bc[0], g.bc[1], fx);
-    const int sj = HASY ? map_index(j0 + ly - GY, g.ny, g.bc[2], g.bc[3], fy) : 0;
+    const int si = map_index(I, g.nx, g.bc[0], g.bc[1], fx);
+    const int sj = HASY ? map_index(J, g.ny, g.bc[2], g.bc[3], fy) : 0;
     const size_t q = (size_t)sj * g.nx + si;
     const double r = a.V[q], mx = a.V[n + q], my = a.V[2 * n + q], E = a.V[3 * n + q];
-    sU[0][k] = (R)r;
-    sU[1][k] = (R)(fx ? -mx : mx);
-    sU[2][k] = (R)(fy ? -my : my);
-    sU[3][k] = (R)E;
-  }
-  __syncthreads();
+    U[0] = (R)r;
+    U[1] = (R)(fx ? -mx : mx);
+    U[2] = (R)(fy ? -my : my);
+    U[3] = (R)E;
+  };
 
   const int tx = tid % TX, ty = tid / TX;
   R D[4];
 
-  // ---- 2. x sweep
+  // ---- 1. x sweep: split fluxes of the tile rows and their x-halo points
+  // (read straight from L2 into registers; only the split fluxes live in LDS),
+  // then one (face, component) per work item, face values parked in registers
+  // until every stencil read is done, then written over the split fluxes.
   {
     const R al = (R)ax;
     for (int k = tid; k < NPX; k += NT) {
       const int j = k / TXP, lx = k - j * TXP;
-      const int src = (j + GY) * TXP + lx;
-      R U[4] = {sU[0][src], sU[1][src], sU[2][src], sU[3][src]};
+      R U[4];
+      load_point(i0 + lx - NG, j0 + j, U);
       R fp[4], fm[4];
       split_flux<0>(U, gamma, gm1, al, fp, fm);
 #pragma unroll
@@ -288,32 +312,43 @@ __global__ __launch_bounds__(TX* TY) void stage_kernel(StageArgs a) {
       }
     }
     __syncthreads();
-    for (int t = tid; t < 4 * NFX; t += NT) {
-      const int f = t % (TX + 1);
-      const int rest = t / (TX + 1);
-      const int j = rest % TY, c = rest / TY;
-      const R* P = &sF[c][j * TXP + f];
-      const R* M = &sF[4 + c][j * TXP + f];
-      const R wp = weno5(P[0], P[1], P[2], P[3], P[4], eps);
-      const R wm = weno5(M[5], M[4], M[3], M[2], M[1], eps);
-      sFh[c][j * (TX + 1) + f] = wp + wm;
+    constexpr int KX = (4 * NFX + NT - 1) / NT;
+    R fh[KX];
+#pragma unroll
+    for (int kk = 0; kk < KX; ++kk) {
+      const int t = tid + kk * NT;  // t = (c * TY + j) * (TX + 1) + f
+      if (t < 4 * NFX) {
+        const int f = t % (TX + 1);
+        const int rest = t / (TX + 1);
+        const int j = rest % TY, c = rest / TY;
+        const R* P = &sF[c][j * TXP + f];
+        const R* M = &sF[4 + c][j * TXP + f];
+        fh[kk] = weno5(P[0], P[1], P[2], P[3], P[4], eps) + weno5(M[5], M[4], M[3], M[2], M[1], eps);
+      }
+    }
+    __syncthreads();
+    R* sFh = &sF[0][0];  // [4][TY][TX + 1], reusing the split-flux storage
+#pragma unroll
+    for (int kk = 0; kk < KX; ++kk) {
+      const int t = tid + kk * NT;
+      if (t < 4 * NFX) sFh[t] = fh[kk];
     }
     __syncthreads();
     const R idx = (R)g.idx;
 #pragma unroll
     for (int c = 0; c < 4; ++c)
-      D[c] = (sFh[c][ty * (TX + 1) + tx + 1] - sFh[c][ty * (TX + 1) + tx]) * idx;
+      D[c] = (sFh[c * NFX + ty * (TX + 1) + tx + 1] - sFh[c * NFX + ty * (TX + 1) + tx]) * idx;
   }
 
-  // ---- 3. y sweep
+  // ---- 2. y sweep (skipped in the 1D limit), same pattern
   R Dy[4] = {R(0), R(0), R(0), R(0)};
   if (HASY) {
-    __syncthreads();  // sF / sFh are reused
+    __syncthreads();  // the x face values are read; sF is reused
     const R al = (R)ay;
     for (int k = tid; k < NPY; k += NT) {
       const int ly = k / TX, i = k - ly * TX;
-      const int src = ly * TXP + i + NG;
-      R U[4] = {sU[0][src], sU[1][src], sU[2][src], sU[3][src]};
+      R U[4];
+      load_point(i0 + i, j0 + ly - GY, U);
       R fp[4], fm[4];
       split_flux<1>(U, gamma, gm1, al, fp, fm);
 #pragma unroll
@@ -323,31 +358,46 @@ __global__ __launch_bounds__(TX* TY) void stage_kernel(StageArgs a) {
       }
     }
     __syncthreads();
-    for (int t = tid; t < 4 * NFY; t += NT) {
-      const int i = t % TX;
-      const int rest = t / TX;
-      const int f = rest % (TY + 1), c = rest / (TY + 1);
-      const R* P = &sF[c][f * TX + i];
-      const R* M = &sF[4 + c][f * TX + i];
-      const R wp = weno5(P[0], P[TX], P[2 * TX], P[3 * TX], P[4 * TX], eps);
-      const R wm = weno5(M[5 * TX], M[4 * TX], M[3 * TX], M[2 * TX], M[TX], eps);
-      sFh[c][f * TX + i] = wp + wm;
+    constexpr int KY = HASY ? (4 * NFY + NT - 1) / NT : 1;
+    R fh[KY];
+#pragma unroll
+    for (int kk = 0; kk < KY; ++kk) {
+      const int t = tid + kk * NT;  // t = (c * (TY + 1) + f) * TX + i
+      if (t < 4 * NFY) {
+        const int i = t % TX;
+        const int rest = t / TX;
+        const int f = rest % (TY + 1), c = rest / (TY + 1);
+        const R* P = &sF[c][f * TX + i];
+        const R* M = &sF[4 + c][f * TX + i];
+        fh[kk] = weno5(P[0], P[TX], P[2 * TX], P[3 * TX], P[4 * TX], eps) +
+                 weno5(M[5 * TX], M[4 * TX], M[3 * TX], M[2 * TX], M[TX], eps);
+      }
+    }
+    __syncthreads();
+    R* sFh = &sF[0][0];  // [4][TY + 1][TX]
+#pragma unroll
+    for (int kk = 0; kk < KY; ++kk) {
+      const int t = tid + kk * NT;
+      if (t < 4 * NFY) sFh[t] = fh[kk];
     }
     __syncthreads();
     const R idy = (R)g.idy;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) Dy[c] = (sFh[c][(ty + 1) * TX + tx] - sFh[c][ty * TX + tx]) * idy;
+    for (int c = 0; c < 4; ++c)
+      Dy[c] = (sFh[c * NFY + (ty + 1) * TX + tx] - sFh[c * NFY + ty * TX + tx]) * idy;
   }
 
-  // ---- 4. per cell: sources, L, stage combination, floor, check, maxima
+  // ---- 3. per cell: sources, L, stage combination, floors, check, maxima
   const int I = i0 + tx, J = j0 + ty;
   const bool act = I < g.nx && J < g.ny;
   double amax = 0.0, bmax = 0.0, smax = 0.0;
   bool bad = false;
   if (act) {
     const size_t q = (size_t)J * g.nx + I;
-    const int cs = (ty + GY) * TXP + tx + NG;
-    const R r = sU[0][cs], mx = sU[1][cs], my = sU[2][cs], E = sU[3][cs];
+    double v[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) v[c] = a.V[c * n + q];
+    const R r = (R)v[0], mx = (R)v[1], my = (R)v[2], E = (R)v[3];
     const R gxv = g.grav ? (R)g.grav[q] : (R)g.gx;
     const R gyv = g.grav ? (R)g.grav[n + q] : (R)g.gy;
     R S[4];
@@ -374,9 +424,8 @@ __global__ __launch_bounds__(TX* TY) void stage_kernel(StageArgs a) {
       double w[4];
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        const double v = a.V[c * n + q];
         const double u0 = a.U0[c * n + q];
-        w[c] = __builtin_fma(a.b, __builtin_fma(dt, (double)L[c], v - u0), u0);
+        w[c] = __builtin_fma(a.b, __builtin_fma(dt, (double)L[c], v[c] - u0), u0);
       }
       if (g.floor_on) {  // atmosphere: minimum density, then minimum pressure
         if (w[0] < g.rho_floor) {
@@ -420,7 +469,7 @@ __global__ __launch_bounds__(TX* TY) void stage_kernel(StageArgs a) {
       bmax = __builtin_fmax(bmax, sRed[k][1]);
       smax = __builtin_fmax(smax, sRed[k][2]);
     }
-    unsigned long long* slot = ctl->slot[(a.stage + 1) % 3];
+    unsigned long long* slot = ctl->slot[(a.stage + 1) % 3][blockIdx.x % NSUB];
     atomicMax(&slot[0], as_bits(amax));
     atomicMax(&slot[1], as_bits(bmax));
     atomicMax(&slot[2], as_bits(smax));

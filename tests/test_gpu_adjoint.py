@@ -4,7 +4,11 @@ package (itself pinned against central differences of the C oracle).
 
 The adjoint is not bit-exact (its sums run in a different order than
 autograd's); the bound is written per test: FP64 relative error of the whole
-vector (L1) <= 1e-12, FP32-bulk <= 2e-5.
+vector (L1) <= 1e-12.  FP32-bulk <= 1e-3: the split fluxes are held in FP32
+(relative rounding 6e-8), and the adjoint differentiates the WENO weights
+through the smoothness indicators, whose neighbour differences d ~ 1e-4 |v|
+in nearly flat regions keep only ~3-4 significant digits; the forward step is
+insensitive to that error (weights saturate), its derivative is not.
 """
 import numpy as np
 import pytest
@@ -118,7 +122,7 @@ def test_step_vjp_fp32_bulk(torch, hydro, oracle_mod):
     want = torch_ref.vjp(prm, None, U0, dt, al, lam)
     s = hydro.Solver(prm, precision=hydro.FP32_BULK)
     got = s.step_vjp(_dev(torch, U0), dt, al, _dev(torch, lam)).cpu().numpy()
-    assert _rel_l1(got, want) <= 2e-5
+    assert _rel_l1(got, want) <= 1e-3
 
 
 def test_floors_rejected_by_vjp(torch, hydro):

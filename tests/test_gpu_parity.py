@@ -236,3 +236,46 @@ def test_invalid_arguments_raise(torch, hydro):
         s.step(torch.zeros((4, 31, 32), dtype=torch.float64, device="cuda"), 1e-3)
     with pytest.raises(TypeError):
         s.step(torch.zeros((4, 32, 32), dtype=torch.float32, device="cuda"), 1e-3)
+
+
+# ------------------------------------------------------------ FP32 bulk form
+# The spatial operator in FP32 (primitives, split fluxes, reconstructions,
+# divergence), the stage combination and reductions in FP64.  Per step the
+# operator's relative error is ~1e-7 (FP32 rounding of O(1) fluxes, a few
+# hundred operations deep), times dt |L| / |U| ~ 0.1 per step; the bounds
+# below (relative L1 of the density against the FP64 oracle) leave a factor
+# of ~10 over that estimate.
+
+@pytest.mark.parametrize("steps,tol", [(1, 1e-7), (10, 1e-6)])
+def test_fp32_bulk_kh_vs_oracle(torch, hydro, oracle_mod, steps, tol):
+    prm, U0 = inputs.kelvin_helmholtz(256, seed=2)
+    want, _, _, _ = oracle_mod.Oracle(prm).run(U0, steps)
+    s = hydro.Solver(prm, precision=hydro.FP32_BULK)
+    U = _dev(torch, U0)
+    s.run(U, steps)
+    got = U.cpu().numpy()
+    err = np.abs(got[0] - want[0]).sum() / np.abs(want[0]).sum()
+    assert err <= tol, err
+    errE = np.abs(got[3] - want[3]).sum() / np.abs(want[3]).sum()
+    assert errE <= tol, errE
+
+
+def test_fp32_bulk_rhs_vs_oracle(torch, hydro, oracle_mod):
+    prm = inputs.make_params(40, 30, 0.0, 1.0, 0.0, 0.8, [R, T, P, P], 1.4, geometry=1, gy=-0.2)
+    U0 = _random_state(30, 40, seed=21)
+    o = oracle_mod.Oracle(prm)
+    want = o.rhs(U0, 2.5, 2.7)
+    got = hydro.Solver(prm, precision=hydro.FP32_BULK).rhs(_dev(torch, U0), 2.5, 2.7).cpu().numpy()
+    err = np.abs(got - want).sum() / np.abs(want).sum()
+    assert err <= 1e-5, err
+
+
+def test_fp32_bulk_sod_vs_oracle(torch, hydro, oracle_mod):
+    prm, U0 = inputs.sod(400)
+    want, t, dts, _ = oracle_mod.Oracle(prm).run(U0, 100000, t_end=0.2)
+    s = hydro.Solver(prm, precision=hydro.FP32_BULK)
+    U = _dev(torch, U0)
+    k, t_gpu, _, _ = s.run(U, len(dts) + 20, t_end=0.2)
+    assert t_gpu == 0.2 and abs(k - len(dts)) <= 1
+    got = U.cpu().numpy()
+    assert np.abs(got[0] - want[0]).sum() / np.abs(want[0]).sum() <= 1e-5

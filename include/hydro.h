@@ -150,6 +150,21 @@ int hydro_rhs(hydro_ctx* ctx, const double* V, double ax, double ay, double* L);
 int hydro_step_vjp(hydro_ctx* ctx, const double* U_n, double dt, const hydro_alpha* alpha,
                    const double* lam_next, double* lam_prev);
 
+/* hydro_step that also keeps its two intermediate stage states: U1_out and
+ * U2_out (device [4][ny][nx], overwritten, distinct from U and each other)
+ * receive U1 = U + dt L(U) and U2 = 3/4 U + 1/4 (U1 + dt L(U1)) of the SSP-RK3
+ * step (Sect. 2.1).  For adjoint replays, which then need not recompute them
+ * (see hydro_step_vjp_saved).  Asynchronous. */
+int hydro_step_save(hydro_ctx* ctx, double* U, double dt, const hydro_alpha* alpha_in,
+                    double* U1_out, double* U2_out);
+
+/* hydro_step_vjp with the step's stage states supplied (as hydro_step_save
+ * wrote them for the same U_n, dt and alpha) instead of recomputed.
+ * lam_prev may not alias any other argument.  Asynchronous. */
+int hydro_step_vjp_saved(hydro_ctx* ctx, const double* U_n, const double* U1, const double* U2,
+                         double dt, const hydro_alpha* alpha, const double* lam_next,
+                         double* lam_prev);
+
 /* Totals of rho, m_x, m_y, E times the cell volume (dx dy; 2 pi r_i dx dy in
  * cylindrical geometry), with compensated (Neumaier) summation in a fixed
  * order.  Synchronises; out_host[4] receives them. */

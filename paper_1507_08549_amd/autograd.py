@@ -5,9 +5,10 @@ device-side CFL step, recording each step's time step and the LF speeds of
 its three stages, and keeps a checkpoint of the state every ``ckpt_every``
 steps.  Its backward pass walks the segments from last to first: it re-runs
 the segment from its checkpoint with the recorded schedule (bit-identical to
-the forward), keeping the state at the start of every step, and then applies
-``hydro_step_vjp`` step by step (each call recomputes that step's two stage
-states).  Memory: nsteps / ckpt_every checkpoints plus ckpt_every states.
+the forward) through ``hydro_step_save``, keeping the state at the start of
+every step and its two Runge-Kutta stage states, and then applies
+``hydro_step_vjp_saved`` step by step.  Memory: nsteps / ckpt_every
+checkpoints plus 3 * ckpt_every states.
 
 The gradient is that of the discrete map with the schedule (dt and alpha of
 every stage) held at its recorded values: those come from maxima over the
@@ -48,19 +49,28 @@ class HydroRollout(torch.autograd.Function):
         als_h = als.cpu().numpy().reshape(-1, 2, 3).transpose(0, 2, 1)  # [n][stage][ax, ay]
         lam = gU.detach().contiguous().clone()
         nxt = torch.empty_like(lam)
+        kmax = min(ctx.ckpt_every, ctx.nsteps)
+        # per step of a segment: its start state and its two stage states
+        pool = [[torch.empty_like(lam) for _ in range(3)] for _ in range(kmax)]
         nseg = len(ctx.ckpts)
         for seg in range(nseg - 1, -1, -1):
             s0 = seg * ctx.ckpt_every
             k = min(ctx.ckpt_every, ctx.nsteps - s0)
-            states = [ctx.ckpts[seg]]
-            U = ctx.ckpts[seg].clone()
-            for i in range(k - 1):
-                solver.step(U, dts_h[s0 + i], alpha=als_h[s0 + i])
-                states.append(U.clone())
+            pool[0][0].copy_(ctx.ckpts[seg])
+            for i in range(k):
+                U, U1, U2 = pool[i]
+                if i + 1 < k:
+                    nxt_state = pool[i + 1][0]
+                    nxt_state.copy_(U)
+                    solver.step_save(nxt_state, dts_h[s0 + i], als_h[s0 + i], U1, U2)
+                else:  # the last step's end state is not needed, only its stages
+                    tmp = nxt
+                    tmp.copy_(U)
+                    solver.step_save(tmp, dts_h[s0 + i], als_h[s0 + i], U1, U2)
             for i in range(k - 1, -1, -1):
-                solver.step_vjp(states[i], dts_h[s0 + i], als_h[s0 + i], lam, out=nxt)
+                U, U1, U2 = pool[i]
+                solver.step_vjp_saved(U, U1, U2, dts_h[s0 + i], als_h[s0 + i], lam, out=nxt)
                 lam, nxt = nxt, lam
-            del states
         return lam, None, None, None
 
 

@@ -140,6 +140,66 @@ int read_flag(hydro_ctx* c, bool clear) {
   return f ? HYDRO_E_UNPHYSICAL : HYDRO_OK;
 }
 
+// One step with the stage states in S1, S2 (the context's scratch or the
+// caller's buffers).
+int step_impl(hydro_ctx* c, double* U, double dt, const hydro_alpha* alpha_in, hydro_alpha* alpha_out,
+              double* S1, double* S2) {
+  if (!alpha_in) HY_CHECK(hy::launch_alpha_reduce(c->g, U, c->ctl, 0, c->apart, c->stream));
+  else HY_CHECK(hy::launch_clear_slots(c->ctl, c->stream));
+  for (int s = 0; s < 3; ++s) {
+    hy::StageArgs a = stage_args(c, U, s);
+    a.V = s == 0 ? U : (s == 1 ? S1 : S2);
+    a.W = s == 0 ? S1 : (s == 1 ? S2 : U);
+    a.dt_mode = 0;
+    a.dt_host = dt;
+    if (alpha_in) {
+      a.frozen = 1;
+      a.fax = alpha_in->ax[s];
+      a.fay = alpha_in->ay[s];
+    }
+    a.alpha_rec = alpha_out ? c->rec : nullptr;
+    HY_CHECK(launch_stage(c, a));
+  }
+  if (alpha_out) {
+    HY_CHECK(hipMemcpyAsync(c->h_buf, c->rec, 6 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HY_CHECK(hipStreamSynchronize(c->stream));
+    for (int s = 0; s < 3; ++s) {
+      alpha_out->ax[s] = c->h_buf[s];
+      alpha_out->ay[s] = c->h_buf[3 + s];
+    }
+  }
+  return HYDRO_OK;
+}
+
+// Adjoint of one step given its two stage states R1, R2.
+int vjp_impl(hydro_ctx* c, const double* U_n, const double* R1, const double* R2, double dt,
+             const hydro_alpha* alpha, const double* lam_next, double* lam_prev) {
+  double* lam2 = c->X[2];
+  double* lam1 = c->X[3];
+  // Stage adjoints, last to first.  With W = U0 + b ((V - U0) + dt L(V)):
+  //   dJ/dV  = b (lam + dt J_L(V)^T lam),  dJ/dU0 += (1 - b) lam.
+  hy::VjpArgs v{};
+  v.g = c->g;
+  v.dt = dt;
+  v.fp32 = c->p.precision == HYDRO_FP32_BULK;
+  v.ghost = c->ghost;
+  v.ghost_y_offset = 2 * 3 * 4 * (size_t)(c->p.nx > c->p.ny ? c->p.nx : c->p.ny);
+  v.Gp = c->X[4];
+  // stage 3 (input R2): lam2 = 2/3 (lam3 + dt J^T lam3);  lam_prev = 1/3 lam3
+  v.V = R2; v.lam = lam_next; v.b = kStageWeight[2]; v.ax = alpha->ax[2]; v.ay = alpha->ay[2];
+  v.out = lam2; v.acc = nullptr; v.side = lam_prev; v.side_in = nullptr;
+  HY_CHECK(hy::launch_stage_vjp(v, c->stream));
+  // stage 2 (input R1): lam1 = 1/4 (lam2 + dt J^T lam2);  lam_prev += 3/4 lam2
+  v.V = R1; v.lam = lam2; v.b = kStageWeight[1]; v.ax = alpha->ax[1]; v.ay = alpha->ay[1];
+  v.out = lam1; v.acc = nullptr; v.side = lam_prev; v.side_in = lam_prev;
+  HY_CHECK(hy::launch_stage_vjp(v, c->stream));
+  // stage 1 (input U_n = U0, b = 1): lam_prev += lam1 + dt J^T lam1
+  v.V = U_n; v.lam = lam1; v.b = kStageWeight[0]; v.ax = alpha->ax[0]; v.ay = alpha->ay[0];
+  v.out = lam_prev; v.acc = lam_prev; v.side = nullptr; v.side_in = nullptr;
+  HY_CHECK(hy::launch_stage_vjp(v, c->stream));
+  return HYDRO_OK;
+}
+
 void free_ctx(hydro_ctx* c) {
   if (!c) return;
   (void)hipFree(c->U1);
@@ -227,29 +287,16 @@ int hydro_step(hydro_ctx* c, double* U, double dt, const hydro_alpha* alpha_in,
   if (!c || !U || !(dt >= 0.0)) return HYDRO_E_INVALID;
   DeviceGuard dg(c->device);
   if (!dg.ok) return HYDRO_E_DEVICE;
-  if (!alpha_in) HY_CHECK(hy::launch_alpha_reduce(c->g, U, c->ctl, 0, c->apart, c->stream));
-  else HY_CHECK(hy::launch_clear_slots(c->ctl, c->stream));
-  for (int s = 0; s < 3; ++s) {
-    hy::StageArgs a = stage_args(c, U, s);
-    a.dt_mode = 0;
-    a.dt_host = dt;
-    if (alpha_in) {
-      a.frozen = 1;
-      a.fax = alpha_in->ax[s];
-      a.fay = alpha_in->ay[s];
-    }
-    a.alpha_rec = alpha_out ? c->rec : nullptr;
-    HY_CHECK(launch_stage(c, a));
-  }
-  if (alpha_out) {
-    HY_CHECK(hipMemcpyAsync(c->h_buf, c->rec, 6 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HY_CHECK(hipStreamSynchronize(c->stream));
-    for (int s = 0; s < 3; ++s) {
-      alpha_out->ax[s] = c->h_buf[s];
-      alpha_out->ay[s] = c->h_buf[3 + s];
-    }
-  }
-  return HYDRO_OK;
+  return step_impl(c, U, dt, alpha_in, alpha_out, c->U1, c->U2);
+}
+
+int hydro_step_save(hydro_ctx* c, double* U, double dt, const hydro_alpha* alpha_in, double* U1_out,
+                    double* U2_out) {
+  if (!c || !U || !U1_out || !U2_out || !(dt >= 0.0)) return HYDRO_E_INVALID;
+  if (U1_out == U || U2_out == U || U1_out == U2_out) return HYDRO_E_INVALID;
+  DeviceGuard dg(c->device);
+  if (!dg.ok) return HYDRO_E_DEVICE;
+  return step_impl(c, U, dt, alpha_in, nullptr, U1_out, U2_out);
 }
 
 int hydro_run(hydro_ctx* c, double* U, int32_t nsteps, double t_end, double* t_io, double* dt_rec,
@@ -305,8 +352,6 @@ int hydro_step_vjp(hydro_ctx* c, const double* U_n, double dt, const hydro_alpha
   // Recompute the stage states with the recorded speeds.
   double* R1 = c->X[0];
   double* R2 = c->X[1];
-  double* lam2 = c->X[2];
-  double* lam1 = c->X[3];
   for (int s = 0; s < 2; ++s) {
     hy::StageArgs a{};
     a.g = c->g;
@@ -323,28 +368,18 @@ int hydro_step_vjp(hydro_ctx* c, const double* U_n, double dt, const hydro_alpha
     a.ctl = c->ctl;
     HY_CHECK(launch_stage(c, a));
   }
-  // Stage adjoints, last to first.  With W = U0 + b ((V - U0) + dt L(V)):
-  //   dJ/dV  = b (lam + dt J_L(V)^T lam),  dJ/dU0 += (1 - b) lam.
-  hy::VjpArgs v{};
-  v.g = c->g;
-  v.dt = dt;
-  v.fp32 = c->p.precision == HYDRO_FP32_BULK;
-  v.ghost = c->ghost;
-  v.ghost_y_offset = 2 * 3 * 4 * (size_t)(c->p.nx > c->p.ny ? c->p.nx : c->p.ny);
-  v.Gp = c->X[4];
-  // stage 3 (input R2): lam2 = 2/3 (lam3 + dt J^T lam3);  lam_prev = 1/3 lam3
-  v.V = R2; v.lam = lam_next; v.b = kStageWeight[2]; v.ax = alpha->ax[2]; v.ay = alpha->ay[2];
-  v.out = lam2; v.acc = nullptr; v.side = lam_prev; v.side_in = nullptr;
-  HY_CHECK(hy::launch_stage_vjp(v, c->stream));
-  // stage 2 (input R1): lam1 = 1/4 (lam2 + dt J^T lam2);  lam_prev += 3/4 lam2
-  v.V = R1; v.lam = lam2; v.b = kStageWeight[1]; v.ax = alpha->ax[1]; v.ay = alpha->ay[1];
-  v.out = lam1; v.acc = nullptr; v.side = lam_prev; v.side_in = lam_prev;
-  HY_CHECK(hy::launch_stage_vjp(v, c->stream));
-  // stage 1 (input U_n = U0, b = 1): lam_prev += lam1 + dt J^T lam1
-  v.V = U_n; v.lam = lam1; v.b = kStageWeight[0]; v.ax = alpha->ax[0]; v.ay = alpha->ay[0];
-  v.out = lam_prev; v.acc = lam_prev; v.side = nullptr; v.side_in = nullptr;
-  HY_CHECK(hy::launch_stage_vjp(v, c->stream));
-  return HYDRO_OK;
+  return vjp_impl(c, U_n, R1, R2, dt, alpha, lam_next, lam_prev);
+}
+
+int hydro_step_vjp_saved(hydro_ctx* c, const double* U_n, const double* U1, const double* U2, double dt,
+                         const hydro_alpha* alpha, const double* lam_next, double* lam_prev) {
+  if (!c || !U_n || !U1 || !U2 || !alpha || !lam_next || !lam_prev) return HYDRO_E_INVALID;
+  if (lam_prev == lam_next || lam_prev == U_n || lam_prev == U1 || lam_prev == U2 || !(dt >= 0.0))
+    return HYDRO_E_INVALID;
+  if (c->g.floor_on) return HYDRO_E_INVALID;
+  DeviceGuard dg(c->device);
+  if (!dg.ok) return HYDRO_E_DEVICE;
+  return vjp_impl(c, U_n, U1, U2, dt, alpha, lam_next, lam_prev);
 }
 
 int hydro_sums(hydro_ctx* c, const double* U, double out_host[4]) {

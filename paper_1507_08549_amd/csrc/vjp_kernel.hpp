@@ -153,14 +153,18 @@ struct VjpPass {
 template <typename R, int DIR, int NA, int NC>
 __global__ __launch_bounds__(256) void vjp_pass_kernel(VjpPass P) {
   constexpr int NT = 256;
-  static_assert(NA * NC == NT, "one tile cell per work item");
   constexpr int LP = NA + 10;  // points with a five-cell halo
   constexpr int LM = NA + 6;   // adjoint values with a three-cell halo
   constexpr int LF = NA + 5;   // faces a0-2 .. a0+NA+2
-  __shared__ R sU[4][NC][LP];
+  static_assert(NA * NC <= NT && LF * NC == NT, "one face per work item, at most one tile cell");
+  // The state tile is only read before the component loop; the per-face
+  // derivative products are only written inside it: they share storage.
+  constexpr int NBUF = (4 * LP > 10 * LF ? 4 * LP : 10 * LF) * NC;
+  __shared__ R sBuf[NBUF];
   __shared__ R sF[8][NC][LP];
   __shared__ R sM[4][NC][LM];
-  __shared__ R sD[10][NC][LF];
+  R(*sU)[NC][LP] = reinterpret_cast<R(*)[NC][LP]>(sBuf);
+  R(*sD)[NC][LF] = reinterpret_cast<R(*)[NC][LF]>(sBuf);
 
   const VjpArgs& a = P.a;
   const Geom& g = a.g;
@@ -215,8 +219,9 @@ __global__ __launch_bounds__(256) void vjp_pass_kernel(VjpPass P) {
   }
   __syncthreads();
 
-  // ---- the points this work item owns: one tile cell, and possibly a ghost
-  const int pb0 = tid / NA, pa0 = tid % NA;  // tile cell
+  // ---- the points this work item owns: at most one tile cell, and possibly a ghost
+  const bool has_cell = tid < NA * NC;
+  const int pb0 = has_cell ? tid / NA : 0, pa0 = has_cell ? tid % NA : 0;
   const bool own_lo = a0 == 0;
   const bool own_hi = a0 <= na - 1 && na - 1 < a0 + NA;
   const int ng = (own_lo ? 3 * NC : 0) + (own_hi ? 3 * NC : 0);
@@ -232,23 +237,27 @@ __global__ __launch_bounds__(256) void vjp_pass_kernel(VjpPass P) {
       gk = na + (t % 3);
     }
   }
-  const bool cell_act = a0 + pa0 < na && b0 + pb0 < nc;
+  const bool cell_act = has_cell && a0 + pa0 < na && b0 + pb0 < nc;
   const bool ghost_act = tid < ng && b0 + gb < nc;
   R dU[4] = {R(0), R(0), R(0), R(0)};
   R dG[4] = {R(0), R(0), R(0), R(0)};
+  R cu[4];  // the cell's own state (for the source terms)
   JacPt<R> jc, jg;
   {
     const int la = pa0 + 5;
-    jc = jac_point<R>(sU[0][pb0][la], sU[1][pb0][la], sU[2][pb0][la], sU[3][pb0][la], gamma, gm1);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) cu[c] = sU[c][pb0][la];
+    jc = jac_point<R>(cu[0], cu[1], cu[2], cu[3], gamma, gm1);
     const int lg = ghost_act ? gk - a0 + 5 : 5;
     const int bb = ghost_act ? gb : 0;
     jg = jac_point<R>(sU[0][bb][lg], sU[1][bb][lg], sU[2][bb][lg], sU[3][bb][lg], gamma, gm1);
   }
+  __syncthreads();  // sU is dead from here; its storage holds sD
 
   for (int c = 0; c < 4; ++c) {
     // per face: nu * dW/dv of both reconstructions of component c
-    for (int t = tid; t < NC * LF; t += NT) {
-      const int b = t / LF, lf = t % LF;
+    {
+      const int b = tid / LF, lf = tid % LF;
       const int f = a0 - 2 + lf;  // global face index (face f: between cells f-1 and f)
       const bool face_in = f >= 0 && f <= na && b0 + b < nc;
       // local mu index of cell f is f - (a0 - 3) = lf + 1
@@ -282,8 +291,10 @@ __global__ __launch_bounds__(256) void vjp_pass_kernel(VjpPass P) {
     };
     {
       R php, phm;
-      gather(a0 + pa0, pb0, php, phm);
-      jacT_row<DIR, R>(c, jc, gamma, gm1, alpha, php + phm, php - phm, dU);
+      if (has_cell) {
+        gather(a0 + pa0, pb0, php, phm);
+        jacT_row<DIR, R>(c, jc, gamma, gm1, alpha, php + phm, php - phm, dU);
+      }
       if (ghost_act) {
         gather(gk, gb, php, phm);
         jacT_row<DIR, R>(c, jg, gamma, gm1, alpha, php + phm, php - phm, dG);
@@ -306,8 +317,7 @@ __global__ __launch_bounds__(256) void vjp_pass_kernel(VjpPass P) {
   double G[4];
   if (DIR == 0) {
     // sources of Eq. euler2D, transposed
-    const int la = pa0 + 5;
-    const R r = sU[0][pb0][la], mx = sU[1][pb0][la], my = sU[2][pb0][la], E = sU[3][pb0][la];
+    const R r = cu[0], E = cu[3];
     const R m0 = sM[0][pb0][pa0 + 3], m1 = sM[1][pb0][pa0 + 3], m2 = sM[2][pb0][pa0 + 3],
             m3 = sM[3][pb0][pa0 + 3];
     const R gxv = g.grav ? (R)g.grav[q] : (R)g.gx;
@@ -327,8 +337,6 @@ __global__ __launch_bounds__(256) void vjp_pass_kernel(VjpPass P) {
       S[1] -= ir * (m0 + R(2) * u * m1 + v * m2 + (gamma * Eo - jc.hq - gm1 * u * u) * m3);
       S[2] -= ir * (u * m2 - gm1 * u * v * m3);
       S[3] -= ir * (gamma * u * m3);
-      (void)mx;
-      (void)my;
     }
 #pragma unroll
     for (int c = 0; c < 4; ++c) G[c] = (double)(S[c] + dU[c]);
@@ -354,32 +362,49 @@ __global__ __launch_bounds__(256) void vjp_pass_kernel(VjpPass P) {
   }
 }
 
-// Adds scale * (adjoint of each ghost point) onto the cell it was copied from,
-// one line per work item, in a fixed order (deterministic, no atomics).
+// Adds scale * (adjoint of each ghost point) onto the cell it was copied from.
+// One work item per (line, component): it loads the six ghost values of its
+// line first, merges those that land on the same cell (transmissive edges, or
+// tiny grids where both sides reach the same cells) in a fixed order, then
+// updates the distinct target cells -- deterministic, no atomics, and no
+// chain of dependent read-modify-writes.
 // (Templated on the pass precision only so each instantiating unit owns a copy.)
 template <typename R>
-__global__ void vjp_fold_kernel(Geom g, int dir, const double* ghost, double* out, double scale) {
+__global__ void vjp_fold_kernel(Geom g, int dir, const double* __restrict__ ghost,
+                                double* __restrict__ out, double scale) {
   const int na = dir == 0 ? g.nx : g.ny;
   const int nc = dir == 0 ? g.ny : g.nx;
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = t >> 2, c = t & 3;
   if (b >= nc) return;
   const int lo = dir == 0 ? g.bc[0] : g.bc[2];
   const int hi = dir == 0 ? g.bc[1] : g.bc[3];
   const int cn = dir == 0 ? 1 : 2;
   const size_t n = (size_t)g.nx * g.ny;
-  for (int side = 0; side < 2; ++side)
-    for (int layer = 0; layer < 3; ++layer) {
-      const int k = side == 0 ? -1 - layer : na + layer;
-      bool flip;
-      const int s = map_index(k, na, lo, hi, flip);
-      const size_t q = dir == 0 ? (size_t)b * g.nx + s : (size_t)s * g.nx + b;
+  int tgt[6];
+  double val[6];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        double v = ghost[(((size_t)side * 3 + layer) * nc + b) * 4 + c];
-        if (flip && c == cn) v = -v;
-        out[c * n + q] += scale * v;
-      }
-    }
+  for (int e = 0; e < 6; ++e) {
+    const int side = e / 3, layer = e % 3;
+    const int k = side == 0 ? -1 - layer : na + layer;
+    bool flip;
+    tgt[e] = map_index(k, na, lo, hi, flip);
+    const double v = ghost[(((size_t)side * 3 + layer) * nc + b) * 4 + c];
+    val[e] = (flip && c == cn) ? -v : v;
+  }
+#pragma unroll
+  for (int e = 0; e < 6; ++e) {
+    bool first = true;
+#pragma unroll
+    for (int f = 0; f < e; ++f) first = first && tgt[f] != tgt[e];
+    if (!first) continue;
+    double sum = val[e];
+#pragma unroll
+    for (int f = e + 1; f < 6; ++f)
+      if (tgt[f] == tgt[e]) sum += val[f];
+    const size_t q = dir == 0 ? (size_t)b * g.nx + tgt[e] : (size_t)tgt[e] * g.nx + b;
+    out[c * n + q] += scale * sum;
+  }
 }
 
 }  // namespace hy

@@ -13,22 +13,22 @@ hipError_t launch_vjp_impl(const VjpArgs& a, hipStream_t s) {
   double* gyb = a.ghost + a.ghost_y_offset;
   const int has_y = g.has_y;
   {
-    constexpr int NA = 64, NC = 4;
+    constexpr int NA = 59, NC = 4;
     VjpPass p{a, a.Gp, has_y ? 0 : 1, gxb};
     const int nb = ((g.nx + NA - 1) / NA) * ((g.ny + NC - 1) / NC);
     hipLaunchKernelGGL((vjp_pass_kernel<R, 0, NA, NC>), dim3(nb), dim3(256), 0, s, p);
   }
   if (has_y) {
-    constexpr int NA = 32, NC = 8;
+    constexpr int NA = 27, NC = 8;
     VjpPass p{a, a.Gp, 1, gyb};
     const int nb = ((g.ny + NA - 1) / NA) * ((g.nx + NC - 1) / NC);
     hipLaunchKernelGGL((vjp_pass_kernel<R, 1, NA, NC>), dim3(nb), dim3(256), 0, s, p);
   }
   const double scale = a.b * a.dt;
-  hipLaunchKernelGGL(vjp_fold_kernel<R>, dim3((g.ny + 255) / 256), dim3(256), 0, s, g, 0,
+  hipLaunchKernelGGL(vjp_fold_kernel<R>, dim3((4 * g.ny + 255) / 256), dim3(256), 0, s, g, 0,
                      (const double*)gxb, a.out, scale);
   if (has_y)
-    hipLaunchKernelGGL(vjp_fold_kernel<R>, dim3((g.nx + 255) / 256), dim3(256), 0, s, g, 1,
+    hipLaunchKernelGGL(vjp_fold_kernel<R>, dim3((4 * g.nx + 255) / 256), dim3(256), 0, s, g, 1,
                        (const double*)gyb, a.out, scale);
   return hipGetLastError();
 }

@@ -56,7 +56,8 @@ _lib = None
 
 #: names of the entry points declared in include/hydro.h
 ENTRY_POINTS = ("hydro_create", "hydro_destroy", "hydro_cfl", "hydro_step", "hydro_run",
-                "hydro_rhs", "hydro_step_vjp", "hydro_sums", "hydro_check", "hydro_strerror")
+                "hydro_rhs", "hydro_step_vjp", "hydro_step_save", "hydro_step_vjp_saved",
+                "hydro_sums", "hydro_check", "hydro_strerror")
 
 
 def declared_entry_points(header: str = HEADER):
@@ -82,6 +83,8 @@ def load():
     lib.hydro_run.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_double, dp, vp, vp]
     lib.hydro_rhs.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double, vp]
     lib.hydro_step_vjp.argtypes = [vp, vp, ctypes.c_double, ctypes.POINTER(Alpha), vp, vp]
+    lib.hydro_step_save.argtypes = [vp, vp, ctypes.c_double, ctypes.POINTER(Alpha), vp, vp]
+    lib.hydro_step_vjp_saved.argtypes = [vp, vp, vp, vp, ctypes.c_double, ctypes.POINTER(Alpha), vp, vp]
     lib.hydro_sums.argtypes = [vp, vp, dp]
     lib.hydro_check.argtypes = [vp]
     lib.hydro_strerror.argtypes = [ip]
@@ -236,6 +239,24 @@ class Solver:
         rc = self._lib.hydro_step_vjp(self._h, self._state(U_n), float(dt), ctypes.byref(a),
                                       self._state(lam_next, "lam_next"), self._state(lam_prev, "lam_prev"))
         self._check(rc, "hydro_step_vjp")
+        return lam_prev
+
+    def step_save(self, U, dt, alpha, U1, U2):
+        """One step in place (alpha: None or (3, 2)), keeping its stage states in U1, U2."""
+        a_in = _alpha_struct(alpha)
+        rc = self._lib.hydro_step_save(self._h, self._state(U), float(dt),
+                                       ctypes.byref(a_in) if a_in is not None else None,
+                                       self._state(U1, "U1"), self._state(U2, "U2"))
+        self._check(rc, "hydro_step_save")
+
+    def step_vjp_saved(self, U_n, U1, U2, dt, alpha, lam_next, out=None):
+        lam_prev = self.new_state() if out is None else out
+        a = _alpha_struct(alpha)
+        rc = self._lib.hydro_step_vjp_saved(self._h, self._state(U_n), self._state(U1, "U1"),
+                                            self._state(U2, "U2"), float(dt), ctypes.byref(a),
+                                            self._state(lam_next, "lam_next"),
+                                            self._state(lam_prev, "lam_prev"))
+        self._check(rc, "hydro_step_vjp_saved")
         return lam_prev
 
     def sums(self, U):

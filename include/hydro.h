@@ -150,13 +150,14 @@ int hydro_rhs(hydro_ctx* ctx, const double* V, double ax, double ay, double* L);
 int hydro_step_vjp(hydro_ctx* ctx, const double* U_n, double dt, const hydro_alpha* alpha,
                    const double* lam_next, double* lam_prev);
 
-/* hydro_step that also keeps its two intermediate stage states: U1_out and
- * U2_out (device [4][ny][nx], overwritten, distinct from U and each other)
- * receive U1 = U + dt L(U) and U2 = 3/4 U + 1/4 (U1 + dt L(U1)) of the SSP-RK3
- * step (Sect. 2.1).  For adjoint replays, which then need not recompute them
- * (see hydro_step_vjp_saved).  Asynchronous. */
-int hydro_step_save(hydro_ctx* ctx, double* U, double dt, const hydro_alpha* alpha_in,
-                    double* U1_out, double* U2_out);
+/* One step U_in -> U_out (U_out may equal U_in) that also keeps its two
+ * intermediate stage states: U1_out and U2_out (device [4][ny][nx],
+ * overwritten, distinct from each other and from U_in, U_out) receive
+ * U1 = U + dt L(U) and U2 = 3/4 U + 1/4 (U1 + dt L(U1)) of the SSP-RK3 step
+ * (Sect. 2.1).  alpha_in as for hydro_step.  For adjoint replays, which then
+ * need not recompute the stages (see hydro_step_vjp_saved).  Asynchronous. */
+int hydro_step_save(hydro_ctx* ctx, const double* U_in, double* U_out, double dt,
+                    const hydro_alpha* alpha_in, double* U1_out, double* U2_out);
 
 /* hydro_step_vjp with the step's stage states supplied (as hydro_step_save
  * wrote them for the same U_n, dt and alpha) instead of recomputed.

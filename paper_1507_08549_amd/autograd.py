@@ -59,14 +59,9 @@ class HydroRollout(torch.autograd.Function):
             pool[0][0].copy_(ctx.ckpts[seg])
             for i in range(k):
                 U, U1, U2 = pool[i]
-                if i + 1 < k:
-                    nxt_state = pool[i + 1][0]
-                    nxt_state.copy_(U)
-                    solver.step_save(nxt_state, dts_h[s0 + i], als_h[s0 + i], U1, U2)
-                else:  # the last step's end state is not needed, only its stages
-                    tmp = nxt
-                    tmp.copy_(U)
-                    solver.step_save(tmp, dts_h[s0 + i], als_h[s0 + i], U1, U2)
+                # the last step's end state is not needed, only its stages
+                dst = pool[i + 1][0] if i + 1 < k else nxt
+                solver.step_save(U, dts_h[s0 + i], als_h[s0 + i], U1, U2, out=dst)
             for i in range(k - 1, -1, -1):
                 U, U1, U2 = pool[i]
                 solver.step_vjp_saved(U, U1, U2, dts_h[s0 + i], als_h[s0 + i], lam, out=nxt)

@@ -140,16 +140,17 @@ int read_flag(hydro_ctx* c, bool clear) {
   return f ? HYDRO_E_UNPHYSICAL : HYDRO_OK;
 }
 
-// One step with the stage states in S1, S2 (the context's scratch or the
-// caller's buffers).
-int step_impl(hydro_ctx* c, double* U, double dt, const hydro_alpha* alpha_in, hydro_alpha* alpha_out,
-              double* S1, double* S2) {
-  if (!alpha_in) HY_CHECK(hy::launch_alpha_reduce(c->g, U, c->ctl, 0, c->apart, c->stream));
-  else HY_CHECK(hy::launch_clear_slots(c->ctl, c->stream));
+// One step U_in -> U_out (may be the same buffer) with the stage states in
+// S1, S2 (the context's scratch or the caller's buffers).
+int step_impl(hydro_ctx* c, const double* U_in, double* U_out, double dt, const hydro_alpha* alpha_in,
+              hydro_alpha* alpha_out, double* S1, double* S2) {
+  // A replay of recorded speeds neither reads nor needs the reduction slots.
+  if (!alpha_in) HY_CHECK(hy::launch_alpha_reduce(c->g, U_in, c->ctl, 0, c->apart, c->stream));
   for (int s = 0; s < 3; ++s) {
-    hy::StageArgs a = stage_args(c, U, s);
-    a.V = s == 0 ? U : (s == 1 ? S1 : S2);
-    a.W = s == 0 ? S1 : (s == 1 ? S2 : U);
+    hy::StageArgs a = stage_args(c, U_out, s);
+    a.U0 = U_in;
+    a.V = s == 0 ? U_in : (s == 1 ? S1 : S2);
+    a.W = s == 0 ? S1 : (s == 1 ? S2 : U_out);
     a.dt_mode = 0;
     a.dt_host = dt;
     if (alpha_in) {
@@ -287,16 +288,17 @@ int hydro_step(hydro_ctx* c, double* U, double dt, const hydro_alpha* alpha_in,
   if (!c || !U || !(dt >= 0.0)) return HYDRO_E_INVALID;
   DeviceGuard dg(c->device);
   if (!dg.ok) return HYDRO_E_DEVICE;
-  return step_impl(c, U, dt, alpha_in, alpha_out, c->U1, c->U2);
+  return step_impl(c, U, U, dt, alpha_in, alpha_out, c->U1, c->U2);
 }
 
-int hydro_step_save(hydro_ctx* c, double* U, double dt, const hydro_alpha* alpha_in, double* U1_out,
-                    double* U2_out) {
-  if (!c || !U || !U1_out || !U2_out || !(dt >= 0.0)) return HYDRO_E_INVALID;
-  if (U1_out == U || U2_out == U || U1_out == U2_out) return HYDRO_E_INVALID;
+int hydro_step_save(hydro_ctx* c, const double* U_in, double* U_out, double dt,
+                    const hydro_alpha* alpha_in, double* U1_out, double* U2_out) {
+  if (!c || !U_in || !U_out || !U1_out || !U2_out || !(dt >= 0.0)) return HYDRO_E_INVALID;
+  if (U1_out == U2_out || U1_out == U_in || U2_out == U_in || U1_out == U_out || U2_out == U_out)
+    return HYDRO_E_INVALID;
   DeviceGuard dg(c->device);
   if (!dg.ok) return HYDRO_E_DEVICE;
-  return step_impl(c, U, dt, alpha_in, nullptr, U1_out, U2_out);
+  return step_impl(c, U_in, U_out, dt, alpha_in, nullptr, U1_out, U2_out);
 }
 
 int hydro_run(hydro_ctx* c, double* U, int32_t nsteps, double t_end, double* t_io, double* dt_rec,

@@ -251,7 +251,7 @@ __global__ __launch_bounds__(TX* TY) void stage_kernel(StageArgs a) {
 
   const double ax = a.frozen || a.rhs_only ? a.fax : sp[0];
   const double ay = a.frozen || a.rhs_only ? a.fay : sp[1];
-  if (!a.rhs_only && blockIdx.x == 0 && tid < NSUB) {
+  if (!a.rhs_only && !a.frozen && blockIdx.x == 0 && tid < NSUB) {
     // clear the slot two stages ahead (one sub-slot per lane)
     unsigned long long* z = ctl->slot[(a.stage + 2) % 3][tid];
     z[0] = 0ull;
@@ -447,6 +447,11 @@ __global__ __launch_bounds__(TX* TY) void stage_kernel(StageArgs a) {
     }
   }
   if (a.rhs_only) return;
+  if (a.frozen) {  // a replay of recorded speeds needs no new maxima, only the check
+    const int anybad = __syncthreads_or(bad ? 1 : 0);
+    if (tid == 0 && anybad) atomicOr(&ctl->flag, 1);
+    return;
+  }
 
   // ---- maxima: wavefront shuffles, then LDS across the workgroup's waves,
   // then one atomic max per quantity (exact and order-free).

@@ -18,8 +18,9 @@
 //     A = dF/dU the flux Jacobian;
 //   * ghost points: their adjoint belongs to the cell they were copied from
 //     (periodic image, mirror with the normal momentum negated, or the edge
-//     cell); it is written to a small side buffer and folded back by a
-//     separate tiny kernel in a fixed order.
+//     cell); it is written to a small side buffer and folded back in a fixed
+//     order: the x ghosts by the y pass at the x-edge cells, the y ghosts (and
+//     the x ghosts in the 1D limit) by a separate tiny kernel.
 // The x and y parts run as two passes (x: sources + x fluxes into a partial
 // sum; y: y fluxes, then the stage combination), each staging a tile with a
 // five-cell halo along its own axis in LDS and processing one component at a
@@ -146,6 +147,7 @@ struct VjpPass {
   double* Gp;      // partial J_L^T mu (x pass writes, y pass reads)
   int finalize;    // this pass writes out / side
   double* ghost;   // ghost adjoints of this pass's axis: [2][3][n_across][4]
+  const double* ghost_x;  // y pass: the x pass's ghost adjoints, merged at the x-edge cells
 };
 
 // One pass (DIR 0: x, with the source adjoint; DIR 1: y) over a tile of NA
@@ -311,9 +313,26 @@ __global__ __launch_bounds__(256) void vjp_pass_kernel(VjpPass P) {
     for (int c = 0; c < 4; ++c)
       P.ghost[(((size_t)side * 3 + layer) * nc + (b0 + gb)) * 4 + c] = (double)dG[c];
   }
-  if (!cell_act) return;
+  // The y pass finalises with the cell index across the axis (x) fastest, so
+  // its global reads and writes are row segments: transpose dU through LDS.
+  int ca = pa0, cb = pb0;
+  bool cact = cell_act;
+  if (DIR == 1) {
+    R(*sT)[NC][NA] = reinterpret_cast<R(*)[NC][NA]>(sBuf);
+    if (has_cell)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) sT[c][pb0][pa0] = dU[c];
+    __syncthreads();
+    cb = tid % NC;
+    ca = tid / NC;
+    cact = has_cell && a0 + ca < na && b0 + cb < nc;
+    if (has_cell)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) dU[c] = sT[c][cb][ca];
+  }
+  if (!cact) return;
 
-  const size_t q = gidx(a0 + pa0, b0 + pb0);
+  const size_t q = gidx(a0 + ca, b0 + cb);
   double G[4];
   if (DIR == 0) {
     // sources of Eq. euler2D, transposed
@@ -343,6 +362,20 @@ __global__ __launch_bounds__(256) void vjp_pass_kernel(VjpPass P) {
   } else {
 #pragma unroll
     for (int c = 0; c < 4; ++c) G[c] = P.Gp[c * n + q] + (double)dU[c];
+    // x-ghost adjoints whose source is this cell (only cells within three of
+    // an x edge can be sources), in a fixed order
+    const int I = b0 + cb, J = a0 + ca;
+    if (I < NG || I >= g.nx - NG) {
+      for (int e = 0; e < 6; ++e) {
+        const int side = e / 3, layer = e % 3;
+        const int k = side == 0 ? -1 - layer : g.nx + layer;
+        bool flip;
+        if (map_index(k, g.nx, g.bc[0], g.bc[1], flip) != I) continue;
+        const double* gv = P.ghost_x + (((size_t)side * 3 + layer) * g.ny + J) * 4;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) G[c] += (flip && c == 1) ? -gv[c] : gv[c];
+      }
+    }
   }
   if (!P.finalize) {
 #pragma unroll

@@ -1,5 +1,6 @@
-// vjp_launch.hpp -- launch sequence of one stage adjoint: x pass, y pass (2D),
-// then the ghost folds (x, then y: corner cells receive both, in this order).
+// vjp_launch.hpp -- launch sequence of one stage adjoint: x pass, y pass (2D;
+// it also merges the x pass's ghost adjoints), then the fold of the remaining
+// ghost adjoints (y in 2D, x in the 1D limit).
 #pragma once
 
 #include "vjp_kernel.hpp"
@@ -14,20 +15,21 @@ hipError_t launch_vjp_impl(const VjpArgs& a, hipStream_t s) {
   const int has_y = g.has_y;
   {
     constexpr int NA = 59, NC = 4;
-    VjpPass p{a, a.Gp, has_y ? 0 : 1, gxb};
+    VjpPass p{a, a.Gp, has_y ? 0 : 1, gxb, nullptr};
     const int nb = ((g.nx + NA - 1) / NA) * ((g.ny + NC - 1) / NC);
     hipLaunchKernelGGL((vjp_pass_kernel<R, 0, NA, NC>), dim3(nb), dim3(256), 0, s, p);
   }
   if (has_y) {
     constexpr int NA = 27, NC = 8;
-    VjpPass p{a, a.Gp, 1, gyb};
+    VjpPass p{a, a.Gp, 1, gyb, gxb};
     const int nb = ((g.ny + NA - 1) / NA) * ((g.nx + NC - 1) / NC);
     hipLaunchKernelGGL((vjp_pass_kernel<R, 1, NA, NC>), dim3(nb), dim3(256), 0, s, p);
   }
   const double scale = a.b * a.dt;
-  hipLaunchKernelGGL(vjp_fold_kernel<R>, dim3((4 * g.ny + 255) / 256), dim3(256), 0, s, g, 0,
-                     (const double*)gxb, a.out, scale);
-  if (has_y)
+  if (!has_y)  // in 2D the y pass has merged the x ghosts
+    hipLaunchKernelGGL(vjp_fold_kernel<R>, dim3((4 * g.ny + 255) / 256), dim3(256), 0, s, g, 0,
+                       (const double*)gxb, a.out, scale);
+  else
     hipLaunchKernelGGL(vjp_fold_kernel<R>, dim3((4 * g.nx + 255) / 256), dim3(256), 0, s, g, 1,
                        (const double*)gyb, a.out, scale);
   return hipGetLastError();

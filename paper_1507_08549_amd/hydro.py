@@ -83,7 +83,7 @@ def load():
     lib.hydro_run.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_double, dp, vp, vp]
     lib.hydro_rhs.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double, vp]
     lib.hydro_step_vjp.argtypes = [vp, vp, ctypes.c_double, ctypes.POINTER(Alpha), vp, vp]
-    lib.hydro_step_save.argtypes = [vp, vp, ctypes.c_double, ctypes.POINTER(Alpha), vp, vp]
+    lib.hydro_step_save.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.POINTER(Alpha), vp, vp]
     lib.hydro_step_vjp_saved.argtypes = [vp, vp, vp, vp, ctypes.c_double, ctypes.POINTER(Alpha), vp, vp]
     lib.hydro_sums.argtypes = [vp, vp, dp]
     lib.hydro_check.argtypes = [vp]
@@ -241,13 +241,16 @@ class Solver:
         self._check(rc, "hydro_step_vjp")
         return lam_prev
 
-    def step_save(self, U, dt, alpha, U1, U2):
-        """One step in place (alpha: None or (3, 2)), keeping its stage states in U1, U2."""
+    def step_save(self, U, dt, alpha, U1, U2, out=None):
+        """One step U -> out (in place if out is None), keeping its stage states in
+        U1, U2.  alpha: None or (3, 2) recorded speeds."""
         a_in = _alpha_struct(alpha)
-        rc = self._lib.hydro_step_save(self._h, self._state(U), float(dt),
+        dst = U if out is None else out
+        rc = self._lib.hydro_step_save(self._h, self._state(U), self._state(dst, "out"), float(dt),
                                        ctypes.byref(a_in) if a_in is not None else None,
                                        self._state(U1, "U1"), self._state(U2, "U2"))
         self._check(rc, "hydro_step_save")
+        return dst
 
     def step_vjp_saved(self, U_n, U1, U2, dt, alpha, lam_next, out=None):
         lam_prev = self.new_state() if out is None else out

@@ -203,7 +203,10 @@ def test_saved_stage_states_reproduce_step_and_vjp(torch, hydro, oracle_mod):
     U = _dev(torch, U0)
     U1 = torch.empty_like(U)
     U2 = torch.empty_like(U)
-    s.step_save(U, dt, al, U1, U2)
+    out = torch.empty_like(U)
+    s.step_save(U, dt, al, U1, U2, out=out)  # out of place
+    assert np.array_equal(out.cpu().numpy(), want) and np.array_equal(U.cpu().numpy(), U0)
+    s.step_save(U, dt, al, U1, U2)  # in place
     assert np.array_equal(U.cpu().numpy(), want)
     # first stage: U + dt L(U) with the oracle's own operator
     L = o.rhs(U0, al[0, 0], al[0, 1])

@@ -11,6 +11,13 @@ Contents
   with fifth-order finite-difference WENO on a global Lax-Friedrichs split,
   the CFL step of Sect. 5.3, compensated totals.  Built by :func:`build` with
   gcc ``-O2 -ffp-contract=off``.
+* ``poisson_oracle.c`` -- plain C: the potential of Sect. 2.1 by red-black
+  successive over-relaxation in (r, z), reflecting axis and plane, Roche
+  outer values; the acceleration -grad Phi.
+* ``levelset_oracle.c`` -- plain C: the level-set flame front of Sect. 2.3,
+  advection of the corner field by Hamilton-Jacobi WENO5 with a global LF
+  flux and SSP-RK3, and re-distancing (front points by linear interpolation,
+  brute-force nearest distance, tanh blend).
 * :mod:`oracle.torch_ref` -- the same update written with plain PyTorch CPU
   fp64 tensor operations; its autograd gives the exact vector-Jacobian
   product of one step with the time step and LF speeds held fixed.
@@ -24,7 +31,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "hydro_oracle.c")
+_SRCS = [os.path.join(_HERE, f) for f in ("hydro_oracle.c", "poisson_oracle.c", "levelset_oracle.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 PERIODIC, TRANSMISSIVE, REFLECTING = 0, 1, 2
@@ -32,14 +39,29 @@ CARTESIAN, CYLINDRICAL = 0, 1
 
 
 def build(force: bool = True) -> str:
-    """Compile ``hydro_oracle.c`` into ``liboracle.so`` next to it."""
+    """Compile the oracle's C sources into ``liboracle.so`` next to them."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         cmd = ["gcc", "-O2", "-mfma", "-ffp-contract=off", "-fno-fast-math", "-std=c99",
-               "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, "-lm"]
+               "-fPIC", "-shared", "-Wall", "-o", tmp, *_SRCS, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
+
+
+class _PoissonParams(ctypes.Structure):
+    _fields_ = [("nr", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("rmax", ctypes.c_double), ("zmax", ctypes.c_double),
+                ("G", ctypes.c_double), ("mass", ctypes.c_double),
+                ("omega", ctypes.c_double), ("tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int32)]
+
+
+class _LsParams(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("xlo", ctypes.c_double), ("xhi", ctypes.c_double),
+                ("ylo", ctypes.c_double), ("yhi", ctypes.c_double),
+                ("bc", ctypes.c_int32 * 4), ("eps", ctypes.c_double)]
 
 
 class _Params(ctypes.Structure):
@@ -77,6 +99,25 @@ def _load():
                   "orc_params_size"):
             getattr(lib, f).restype = ctypes.c_int
         assert lib.orc_params_size() == ctypes.sizeof(_Params)
+        lib.orc_poisson.argtypes = [ctypes.POINTER(_PoissonParams), dp, dp, dp]
+        lib.orc_poisson.restype = ctypes.c_int
+        lib.orc_gravity.argtypes = [ctypes.POINTER(_PoissonParams), dp, dp]
+        lib.orc_gravity.restype = None
+        lib.orc_poisson_params_size.restype = ctypes.c_int
+        assert lib.orc_poisson_params_size() == ctypes.sizeof(_PoissonParams)
+        lp = ctypes.POINTER(_LsParams)
+        lib.orc_ls_alpha.argtypes = [lp, dp, ctypes.c_double, dp]
+        lib.orc_ls_alpha.restype = None
+        lib.orc_ls_rhs.argtypes = [lp, dp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
+        lib.orc_ls_rhs.restype = None
+        lib.orc_ls_step.argtypes = [lp, dp, dp, ctypes.c_double, ctypes.c_double]
+        lib.orc_ls_step.restype = None
+        lib.orc_ls_front.argtypes = [lp, dp, dp, ctypes.c_long]
+        lib.orc_ls_front.restype = ctypes.c_long
+        lib.orc_ls_redistance.argtypes = [lp, dp, dp]
+        lib.orc_ls_redistance.restype = ctypes.c_long
+        lib.orc_ls_params_size.restype = ctypes.c_int
+        assert lib.orc_ls_params_size() == ctypes.sizeof(_LsParams)
         _lib = lib
     return _lib
 
@@ -184,3 +225,98 @@ class Oracle:
         out = np.zeros(4)
         _chk(self._lib.orc_sums(ctypes.byref(self._p), _ptr(U), _ptr(out)))
         return out
+
+
+def _poisson_params(nr, nz, rmax, zmax, G, mass, omega=1.9, tol=1e-8, max_iter=100000):
+    q = _PoissonParams()
+    q.nr, q.nz = int(nr), int(nz)
+    q.rmax, q.zmax = float(rmax), float(zmax)
+    q.G, q.mass = float(G), float(mass)
+    q.omega, q.tol, q.max_iter = float(omega), float(tol), int(max_iter)
+    return q
+
+
+def poisson(rho, rmax, zmax, G, mass, phi0=None, omega=1.9, tol=1e-8, max_iter=100000):
+    """Potential of density rho ((nz, nr), quarter plane r, z >= 0) by red-black
+    SOR from phi0 (default 0).  Returns (phi, iterations, last relative change)."""
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    nz, nr = rho.shape
+    phi = np.zeros_like(rho) if phi0 is None else np.array(phi0, dtype=np.float64, copy=True)
+    q = _poisson_params(nr, nz, rmax, zmax, G, mass, omega, tol, max_iter)
+    ch = np.zeros(1)
+    it = _load().orc_poisson(ctypes.byref(q), _ptr(rho), _ptr(phi), _ptr(ch))
+    if it < 0:
+        raise OracleError("poisson: invalid parameters")
+    return phi, it, float(ch[0])
+
+
+def gravity_from_potential(phi, rmax, zmax, G, mass):
+    """-grad phi at the cell centres, (2, nz, nr) = (g_r, g_z)."""
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    nz, nr = phi.shape
+    q = _poisson_params(nr, nz, rmax, zmax, G, mass)
+    g = np.zeros((2, nz, nr))
+    _load().orc_gravity(ctypes.byref(q), _ptr(phi), _ptr(g))
+    return g
+
+
+class LevelSet:
+    """The level-set oracle on the corners of a grid.
+
+    ``params`` uses the keys nx, ny, xlo, xhi, ylo, yhi, bc (4 ints) and eps of
+    the fluid's parameters.  Fields are float64 arrays of shape (ny+1, nx+1);
+    corner velocities (2, ny+1, nx+1)."""
+
+    def __init__(self, params: dict):
+        q = _LsParams()
+        q.nx, q.ny = int(params["nx"]), int(params["ny"])
+        q.xlo, q.xhi = float(params["xlo"]), float(params["xhi"])
+        q.ylo, q.yhi = float(params["ylo"]), float(params["yhi"])
+        for k, b in enumerate(params["bc"]):
+            q.bc[k] = int(b)
+        q.eps = float(params.get("eps", 1e-6))
+        self._q = q
+        self.shape = (q.ny + 1, q.nx + 1)
+        self._lib = _load()
+
+    def _f(self, S):
+        S = np.ascontiguousarray(S, dtype=np.float64)
+        assert S.shape == self.shape, S.shape
+        return S
+
+    def _v(self, vel):
+        vel = np.ascontiguousarray(vel, dtype=np.float64)
+        assert vel.shape == (2,) + self.shape, vel.shape
+        return vel
+
+    def alpha(self, vel, s_f=0.0):
+        out = np.zeros(2)
+        self._lib.orc_ls_alpha(ctypes.byref(self._q), _ptr(self._v(vel)), float(s_f), _ptr(out))
+        return out
+
+    def rhs(self, S, vel, s_f, ax, ay):
+        S = self._f(S)
+        L = np.empty_like(S)
+        self._lib.orc_ls_rhs(ctypes.byref(self._q), _ptr(S), _ptr(self._v(vel)), float(s_f),
+                             float(ax), float(ay), _ptr(L))
+        return L
+
+    def step(self, S, vel, s_f, dt):
+        S = self._f(S).copy()
+        self._lib.orc_ls_step(ctypes.byref(self._q), _ptr(S), _ptr(self._v(vel)), float(s_f), float(dt))
+        return S
+
+    def front(self, S):
+        """Front points, (n, 2) = (x, y), in the oracle's order."""
+        S = self._f(S)
+        cap = 3 * S.size
+        pts = np.zeros((cap, 2))
+        n = self._lib.orc_ls_front(ctypes.byref(self._q), _ptr(S), _ptr(pts), cap)
+        return pts[:n].copy()
+
+    def redistance(self, S):
+        """Returns (S_new, d, number of front points); d is None without front points."""
+        S = self._f(S).copy()
+        d = np.full_like(S, np.nan)
+        n = self._lib.orc_ls_redistance(ctypes.byref(self._q), _ptr(S), _ptr(d))
+        return S, (d if n > 0 else None), int(n)

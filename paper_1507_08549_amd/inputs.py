@@ -308,3 +308,47 @@ def explosion(n=512, gamma=1.4, cfl=0.5):
     inside = X * X + Y * Y < 0.16
     return prm, state_from_primitive(np.where(inside, 1.0, 0.125), 0.0, 0.0,
                                      np.where(inside, 1.0, 0.1), gamma)
+
+
+def corners(params):
+    """Corner coordinates (x of shape (nx+1,), y of shape (ny+1,))."""
+    nx, ny = params["nx"], params["ny"]
+    dx = (params["xhi"] - params["xlo"]) / nx
+    dy = (params["yhi"] - params["ylo"]) / ny
+    return params["xlo"] + np.arange(nx + 1) * dx, params["ylo"] + np.arange(ny + 1) * dy
+
+
+def single_vortex(params, t=0.0, period=0.0):
+    """Corner velocity (2, ny+1, nx+1) of the deforming single vortex on the unit
+    square, u = -sin^2(pi x) sin(2 pi y), v = sin^2(pi y) sin(2 pi x), times
+    cos(pi t / period) when a period is given."""
+    x, y = corners(params)
+    X, Y = np.meshgrid(x, y)
+    f = math.cos(math.pi * t / period) if period > 0 else 1.0
+    u = -f * np.sin(np.pi * X) ** 2 * np.sin(2 * np.pi * Y)
+    v = f * np.sin(np.pi * Y) ** 2 * np.sin(2 * np.pi * X)
+    return np.ascontiguousarray(np.stack([u, v]))
+
+
+def flame_front(n=1024, seed=6, R0=0.2, modes=8, amp=0.03, slope=1.5, s_f=0.02):
+    """Level-set workload on the (n+1)^2 corners of the unit square: ash (S > 0)
+    inside a circle of radius R0 centred at (0.5, 0.75) whose radius carries
+    seeded modes, R(theta) = R0 (1 + sum_k a_k cos(k theta + phi_k)),
+    k = 2..modes+1, a_k ~ N(0, amp), phi_k ~ U(0, 2 pi); S = slope (R(theta) - r)
+    (not a distance function unless slope = 1 and amp = 0); the single-vortex
+    corner velocity; transmissive edges; laminar flame speed s_f.
+    Returns (params, S, vel, s_f)."""
+    prm = make_params(n, n, 0.0, 1.0, 0.0, 1.0, [TRANSMISSIVE] * 4, 1.4)
+    x, y = corners(prm)
+    X, Y = np.meshgrid(x, y)
+    dxc, dyc = X - 0.5, Y - 0.75
+    r = np.sqrt(dxc * dxc + dyc * dyc)
+    th = np.arctan2(dyc, dxc)
+    rng = np.random.default_rng(seed)
+    a = rng.normal(0.0, amp, modes)
+    ph = rng.uniform(0.0, 2 * np.pi, modes)
+    Rt = np.ones_like(r)
+    for k in range(modes):
+        Rt = Rt + a[k] * np.cos((k + 2) * th + ph[k])
+    S = slope * (R0 * Rt - r)
+    return prm, np.ascontiguousarray(S), single_vortex(prm), float(s_f)

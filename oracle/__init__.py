@@ -73,6 +73,7 @@ class _Params(ctypes.Structure):
         ("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("eps", ctypes.c_double),
         ("gx", ctypes.c_double), ("gy", ctypes.c_double),
         ("rho_floor", ctypes.c_double), ("p_floor", ctypes.c_double),
+        ("recon", ctypes.c_int32),
     ]
 
 
@@ -99,6 +100,8 @@ def _load():
                   "orc_params_size"):
             getattr(lib, f).restype = ctypes.c_int
         assert lib.orc_params_size() == ctypes.sizeof(_Params)
+        lib.orc_char_eig.argtypes = [dp, dp, ctypes.c_int, ctypes.c_double, dp, dp]
+        lib.orc_char_eig.restype = ctypes.c_int
         lib.orc_poisson.argtypes = [ctypes.POINTER(_PoissonParams), dp, dp, dp]
         lib.orc_poisson.restype = ctypes.c_int
         lib.orc_gravity.argtypes = [ctypes.POINTER(_PoissonParams), dp, dp]
@@ -116,6 +119,8 @@ def _load():
         lib.orc_ls_front.restype = ctypes.c_long
         lib.orc_ls_redistance.argtypes = [lp, dp, dp]
         lib.orc_ls_redistance.restype = ctypes.c_long
+        lib.orc_ls_corner_velocity.argtypes = [lp, dp, dp]
+        lib.orc_ls_corner_velocity.restype = None
         lib.orc_ls_params_size.restype = ctypes.c_int
         assert lib.orc_ls_params_size() == ctypes.sizeof(_LsParams)
         _lib = lib
@@ -137,6 +142,17 @@ def _chk(rc):
         names = {-1: "invalid argument", -2: "out of memory", -4: "unphysical state (rho<=0 or p<=0)"}
         raise OracleError(f"oracle error {rc}: {names.get(rc, '?')}")
     return rc
+
+
+def char_eig(Ul, Ur, direction, gamma):
+    """(L, R) (4x4 each) of the characteristic reconstruction at the Roe
+    average of two conserved states, in the rotated frame (rho, m_n, m_t, E)."""
+    Ul = np.ascontiguousarray(Ul, dtype=np.float64)
+    Ur = np.ascontiguousarray(Ur, dtype=np.float64)
+    L = np.zeros(16)
+    R = np.zeros(16)
+    _chk(_load().orc_char_eig(_ptr(Ul), _ptr(Ur), int(direction), float(gamma), _ptr(L), _ptr(R)))
+    return L.reshape(4, 4), R.reshape(4, 4)
 
 
 def weno5(v, eps=1e-6):
@@ -168,6 +184,7 @@ class Oracle:
         p.gx, p.gy = float(params.get("gx", 0.0)), float(params.get("gy", 0.0))
         p.rho_floor = float(params.get("rho_floor", 0.0))
         p.p_floor = float(params.get("p_floor", 0.0))
+        p.recon = int(params.get("recon", 0))
         self._p = p
         self.nx, self.ny = p.nx, p.ny
         self.gravity = None
@@ -289,6 +306,14 @@ class LevelSet:
         assert vel.shape == (2,) + self.shape, vel.shape
         return vel
 
+    def corner_velocity(self, U):
+        """Corner velocity (2, ny+1, nx+1) from a cell state (4, ny, nx)."""
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        assert U.shape == (4, self.shape[0] - 1, self.shape[1] - 1), U.shape
+        vel = np.empty((2,) + self.shape)
+        self._lib.orc_ls_corner_velocity(ctypes.byref(self._q), _ptr(U), _ptr(vel))
+        return vel
+
     def alpha(self, vel, s_f=0.0):
         out = np.zeros(2)
         self._lib.orc_ls_alpha(ctypes.byref(self._q), _ptr(self._v(vel)), float(s_f), _ptr(out))
@@ -313,6 +338,19 @@ class LevelSet:
         pts = np.zeros((cap, 2))
         n = self._lib.orc_ls_front(ctypes.byref(self._q), _ptr(S), _ptr(pts), cap)
         return pts[:n].copy()
+
+    def distance_at(self, S, js, is_):
+        """Nearest-front distance of the corners (js[k], is_[k]) by brute force over
+        this oracle's front points (the same operations as the C routine)."""
+        pts = self.front(S)
+        q = self._q
+        dx = (q.xhi - q.xlo) / q.nx
+        dy = (q.yhi - q.ylo) / q.ny
+        x = q.xlo + np.asarray(is_, dtype=np.float64) * dx
+        y = q.ylo + np.asarray(js, dtype=np.float64) * dy
+        ex = x[:, None] - pts[None, :, 0]
+        ey = y[:, None] - pts[None, :, 1]
+        return np.sqrt(ex * ex + ey * ey).min(axis=1)
 
     def redistance(self, S):
         """Returns (S_new, d, number of front points); d is None without front points."""

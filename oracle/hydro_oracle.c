@@ -34,7 +34,11 @@
  *  - ghost cells: periodic, transmissive (zero gradient, the paper's "free"
  *    boundary) or reflecting (mirror, normal momentum negated; the r = 0 axis
  *    and the z = 0 plane of Eq. euler2D are reflecting);
- *  - geometric sources of Eq. euler2D evaluated at r_i = xlo + (i+1/2) dx.
+ *  - geometric sources of Eq. euler2D evaluated at r_i = xlo + (i+1/2) dx;
+ *  - the paper names its scheme "WENO-Roe": besides the component-wise
+ *    reconstruction of the split fluxes (what its text describes), recon = 1
+ *    reconstructs them in the characteristic fields of the flux Jacobian at
+ *    the Roe average of the two cells beside each face (char_face below).
  *
  * Rounding contract.  Every formula is written in one fixed evaluation
  * order; fma(a,b,c) is a single-rounding a*b+c (C99).  Build with
@@ -64,6 +68,7 @@ typedef struct {
   double gamma, cfl, eps;
   double gx, gy;              /* uniform gravity (used when no field is given) */
   double rho_floor, p_floor;  /* atmosphere floors applied after each stage when rho_floor > 0 */
+  int32_t recon;              /* 0 component-wise, 1 characteristic-wise reconstruction */
 } orc_params;
 
 /* ---------------------------------------------------------------- helpers */
@@ -79,6 +84,7 @@ static int check_params(const orc_params *p) {
   if ((p->bc[2] == ORC_PERIODIC) != (p->bc[3] == ORC_PERIODIC)) return ORC_E_INVALID;
   if (p->geometry == 1 && p->xlo < 0.0) return ORC_E_INVALID;
   if (p->geometry != 0 && p->geometry != 1) return ORC_E_INVALID;
+  if (p->recon != 0 && p->recon != 1) return ORC_E_INVALID;
   return ORC_OK;
 }
 
@@ -272,6 +278,90 @@ static void split_flux(const double U[4], double gamma, double alpha, int dir,
   }
 }
 
+/* Eigenvectors of the flux Jacobian in direction dir at the Roe average of
+ * the states Ul, Ur (conserved, (rho, m_x, m_y, E)), in the rotated frame
+ * (rho, m_n, m_t, E) with n the direction of the sweep and t the other one:
+ * right eigenvectors (columns) for the speeds u_n - c, u_n, u_n, u_n + c
+ *   R = [1, 1, 0, 1; u_n - c, u_n, 0, u_n + c; u_t, u_t, 1, u_t;
+ *        H - u_n c, q2/2, u_t, H + u_n c],
+ * and their inverse L (rows), b1 = (gamma - 1)/c^2, b2 = b1 q2/2:
+ *   L = [(b2 + u_n/c)/2, (-b1 u_n - 1/c)/2, -b1 u_t/2, b1/2;
+ *        1 - b2, b1 u_n, b1 u_t, -b1;  -u_t, 0, 1, 0;
+ *        (b2 - u_n/c)/2, (1/c - b1 u_n)/2, -b1 u_t/2, b1/2].
+ * Roe average: weights sqrt(rho); u_n, u_t and the total enthalpy
+ * H = (E + p)/rho averaged, c^2 = (gamma - 1)(H - q2/2), q2 = u_n^2 + u_t^2.
+ * Returns ORC_E_UNPHYSICAL when c^2 <= 0. */
+int orc_char_eig(const double Ul[4], const double Ur[4], int dir, double gamma, double Lm[16],
+                 double Rm[16]) {
+  prim_t wl = cons_to_prim(Ul[0], Ul[1], Ul[2], Ul[3], gamma);
+  prim_t wr = cons_to_prim(Ur[0], Ur[1], Ur[2], Ur[3], gamma);
+  const double nl = dir == 0 ? wl.u : wl.v, tl = dir == 0 ? wl.v : wl.u;
+  const double nr = dir == 0 ? wr.u : wr.v, tr = dir == 0 ? wr.v : wr.u;
+  const double Hl = (Ul[3] + wl.p) / Ul[0], Hr = (Ur[3] + wr.p) / Ur[0];
+  const double sl = sqrt(Ul[0]), sr = sqrt(Ur[0]);
+  const double den = sl + sr;
+  const double un = (sl * nl + sr * nr) / den;
+  const double ut = (sl * tl + sr * tr) / den;
+  const double H = (sl * Hl + sr * Hr) / den;
+  const double q2 = un * un + ut * ut;
+  const double c2 = (gamma - 1.0) * (H - 0.5 * q2);
+  if (!(c2 > 0.0) || !isfinite(c2)) return ORC_E_UNPHYSICAL;
+  const double c = sqrt(c2), ic = 1.0 / c;
+  const double b1 = (gamma - 1.0) / c2, b2 = (0.5 * q2) * b1;
+  const double L[16] = {0.5 * (b2 + un * ic), 0.5 * (-(b1 * un) - ic), -0.5 * (b1 * ut), 0.5 * b1,
+                        1.0 - b2, b1 * un, b1 * ut, -b1,
+                        -ut, 0.0, 1.0, 0.0,
+                        0.5 * (b2 - un * ic), 0.5 * (ic - b1 * un), -0.5 * (b1 * ut), 0.5 * b1};
+  const double R[16] = {1.0, 1.0, 0.0, 1.0,
+                        un - c, un, 0.0, un + c,
+                        ut, ut, 1.0, ut,
+                        H - un * c, 0.5 * q2, ut, H + un * c};
+  memcpy(Lm, L, sizeof(L));
+  memcpy(Rm, R, sizeof(R));
+  return ORC_OK;
+}
+
+/* Four-term dot product in a fixed order: ((a0 b0 + a1 b1) + a2 b2) + a3 b3,
+ * each step one fma. */
+static double dot4(const double *a, const double b[4]) {
+  return fma(a[3], b[3], fma(a[2], b[2], fma(a[1], b[1], a[0] * b[0])));
+}
+
+/* Characteristic-wise face value between padded points i and i+1 of a line:
+ * fp, fm hold the split fluxes of the line ([k][4], original component
+ * order), Ul, Ur the states at i and i+1.  Each field m: the projections
+ * l_m . f+ at i-2..i+2 reconstructed left-biased plus l_m . f- at i+3..i-1
+ * right-biased; the face flux is R times those four values, rotated back. */
+static int char_face(const double *fp, const double *fm, int i, const double Ul[4],
+                     const double Ur[4], int dir, double gamma, double eps, double out[4]) {
+  double L[16], R[16];
+  int rc = orc_char_eig(Ul, Ur, dir, gamma, L, R);
+  if (rc) return rc;
+  const int cn = dir == 0 ? 1 : 2, ct = dir == 0 ? 2 : 1;
+  double gp[6][4], gm[6][4]; /* rotated split fluxes at i-2 .. i+3 */
+  for (int k = 0; k < 6; ++k) {
+    const int q = i - 2 + k;
+    gp[k][0] = fp[4 * q]; gp[k][1] = fp[4 * q + cn]; gp[k][2] = fp[4 * q + ct]; gp[k][3] = fp[4 * q + 3];
+    gm[k][0] = fm[4 * q]; gm[k][1] = fm[4 * q + cn]; gm[k][2] = fm[4 * q + ct]; gm[k][3] = fm[4 * q + 3];
+  }
+  double gh[4];
+  for (int m = 0; m < 4; ++m) {
+    const double *l = &L[4 * m];
+    const double wp = orc_weno5(dot4(l, gp[0]), dot4(l, gp[1]), dot4(l, gp[2]), dot4(l, gp[3]),
+                                dot4(l, gp[4]), eps);
+    const double wm = orc_weno5(dot4(l, gm[5]), dot4(l, gm[4]), dot4(l, gm[3]), dot4(l, gm[2]),
+                                dot4(l, gm[1]), eps);
+    gh[m] = wp + wm;
+  }
+  double rot[4];
+  for (int c = 0; c < 4; ++c) rot[c] = dot4(&R[4 * c], gh);
+  out[0] = rot[0];
+  out[cn] = rot[1];
+  out[ct] = rot[2];
+  out[3] = rot[3];
+  return ORC_OK;
+}
+
 /* L(V) on the interior for given LF speeds (ax, ay).  gravity: NULL or
  * [2][ny][nx] (g_x, g_y) per cell.  L: [4][ny][nx]. */
 int orc_rhs(const orc_params *p, const double *gravity, const double *V,
@@ -302,6 +392,7 @@ int orc_rhs(const orc_params *p, const double *gravity, const double *V,
     return ORC_E_NOMEM;
   }
   fill_padded(p, V, &P);
+  int status = ORC_OK;
 
   /* x sweep, one interior row at a time.  Padded point k <-> cell k - NG.
    * Face f (0..nx) sits between cells f-1 and f. */
@@ -314,6 +405,15 @@ int orc_rhs(const orc_params *p, const double *gravity, const double *V,
     }
     for (int f = 0; f <= nx; ++f) {
       int i = f - 1 + NG; /* padded index of the cell left of the face */
+      if (p->recon == 1) {
+        double Ul[4], Ur[4];
+        for (int c = 0; c < 4; ++c) {
+          Ul[c] = *pad_at(&P, c, j, i - NG);
+          Ur[c] = *pad_at(&P, c, j, i + 1 - NG);
+        }
+        if (char_face(fp, fm, i, Ul, Ur, 0, p->gamma, eps, &Fh[4 * f])) status = ORC_E_UNPHYSICAL;
+        continue;
+      }
       for (int c = 0; c < 4; ++c) {
         double wp = orc_weno5(fp[4 * (i - 2) + c], fp[4 * (i - 1) + c], fp[4 * i + c],
                               fp[4 * (i + 1) + c], fp[4 * (i + 2) + c], eps);
@@ -338,6 +438,15 @@ int orc_rhs(const orc_params *p, const double *gravity, const double *V,
       }
       for (int f = 0; f <= ny; ++f) {
         int jj = f - 1 + NG;
+        if (p->recon == 1) {
+          double Ul[4], Ur[4];
+          for (int c = 0; c < 4; ++c) {
+            Ul[c] = *pad_at(&P, c, jj - NG, i);
+            Ur[c] = *pad_at(&P, c, jj + 1 - NG, i);
+          }
+          if (char_face(fp, fm, jj, Ul, Ur, 1, p->gamma, eps, &Fh[4 * f])) status = ORC_E_UNPHYSICAL;
+          continue;
+        }
         for (int c = 0; c < 4; ++c) {
           double wp = orc_weno5(fp[4 * (jj - 2) + c], fp[4 * (jj - 1) + c], fp[4 * jj + c],
                                 fp[4 * (jj + 1) + c], fp[4 * (jj + 2) + c], eps);
@@ -380,7 +489,7 @@ int orc_rhs(const orc_params *p, const double *gravity, const double *V,
     }
 
   free(P.a); free(Dx); free(Dy); free(fp); free(fm); free(Fh);
-  return ORC_OK;
+  return status;
 }
 
 /* --------------------------------------------------------------- stepping */

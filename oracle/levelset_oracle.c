@@ -32,7 +32,7 @@
  *    increment form of the fluid's step, with a given dt;
  *  - ghost corners (3 per side): periodic (corner nx is corner 0's image, so the
  *    grid is nx x ny distinct corners and corner nx/ny is overwritten by its
- *    image after each stage), reflecting (S_{-k} = S_k about the wall corner),
+ *    image before the step and after each stage), reflecting (S_{-k} = S_k about the wall corner),
  *    transmissive (linear extrapolation S_{-k} = 2 S_0 - S_k, which keeps a
  *    distance function's slope);
  *  - (2): front points on corner-to-corner edges (horizontal and vertical) with
@@ -170,6 +170,7 @@ void orc_ls_step(const orc_ls_params *q, double *S, const double *vel, double s_
   orc_ls_alpha(q, vel, s_f, a);
   double *S0 = malloc(sizeof(double) * n), *V = malloc(sizeof(double) * n),
          *L = malloc(sizeof(double) * n);
+  periodic_images(q, S); /* corner nx (ny) is corner 0's image from the start */
   memcpy(S0, S, sizeof(double) * n);
   memcpy(V, S, sizeof(double) * n);
   const double b[3] = {1.0, 0.25, 2.0 / 3.0};
@@ -259,6 +260,55 @@ long orc_ls_redistance(const orc_ls_params *q, double *S, double *dist) {
   }
   free(pts);
   return np;
+}
+
+/* Corner velocity from a cell state U[4][ny][nx] (rho, m_x, m_y, E): the mean
+ * of the velocities m/rho of the four cells that share the corner,
+ * 0.25 ((a + b) + (c + d)) with a, b the lower-left and lower-right cell and
+ * c, d the upper ones.  Beyond the grid the fluid's ghost cells stand in:
+ * periodic images, copies of the edge cell (transmissive), or mirror cells
+ * with the normal velocity negated (reflecting, which makes it 0 on the wall).
+ * vel: [2][ny+1][nx+1]. */
+static void cell_velocity(const orc_ls_params *q, const double *U, int ci, int cj, double *u, double *v) {
+  const int nx = q->nx, ny = q->ny;
+  double su = 1.0, sv = 1.0;
+  if (ci < 0) {
+    if (q->bc[0] == LS_PERIODIC) ci += nx;
+    else if (q->bc[0] == LS_REFLECTING) { ci = -1 - ci; su = -1.0; }
+    else ci = 0;
+  } else if (ci >= nx) {
+    if (q->bc[1] == LS_PERIODIC) ci -= nx;
+    else if (q->bc[1] == LS_REFLECTING) { ci = 2 * nx - 1 - ci; su = -1.0; }
+    else ci = nx - 1;
+  }
+  if (cj < 0) {
+    if (q->bc[2] == LS_PERIODIC) cj += ny;
+    else if (q->bc[2] == LS_REFLECTING) { cj = -1 - cj; sv = -1.0; }
+    else cj = 0;
+  } else if (cj >= ny) {
+    if (q->bc[3] == LS_PERIODIC) cj -= ny;
+    else if (q->bc[3] == LS_REFLECTING) { cj = 2 * ny - 1 - cj; sv = -1.0; }
+    else cj = ny - 1;
+  }
+  const size_t n = (size_t)nx * (size_t)ny, k = (size_t)cj * nx + ci;
+  const double rho = U[k];
+  *u = su * (U[n + k] / rho);
+  *v = sv * (U[2 * n + k] / rho);
+}
+
+void orc_ls_corner_velocity(const orc_ls_params *q, const double *U, double *vel) {
+  const int mx = q->nx + 1, my = q->ny + 1;
+  const size_t nc = (size_t)mx * (size_t)my;
+  for (int j = 0; j < my; ++j)
+    for (int i = 0; i < mx; ++i) {
+      double ua, va, ub, vb, uc, vc, ud, vd;
+      cell_velocity(q, U, i - 1, j - 1, &ua, &va);
+      cell_velocity(q, U, i, j - 1, &ub, &vb);
+      cell_velocity(q, U, i - 1, j, &uc, &vc);
+      cell_velocity(q, U, i, j, &ud, &vd);
+      vel[(size_t)j * mx + i] = 0.25 * ((ua + ub) + (uc + ud));
+      vel[nc + (size_t)j * mx + i] = 0.25 * ((va + vb) + (vc + vd));
+    }
 }
 
 int orc_ls_params_size(void) { return (int)sizeof(orc_ls_params); }

@@ -193,3 +193,26 @@ def test_circular_flame_grows_at_the_flame_speed(oracle_mod):
         k = np.nonzero(row < 0)[0][0]
         rad = (k - 1 + row[k - 1] / (row[k - 1] - row[k])) / n
         assert abs(rad - (0.2 + t)) < 0.05 / n, (rad, 0.2 + t)
+
+
+def test_corner_velocity(oracle_mod):
+    """Linear velocity fields are reproduced exactly at interior corners (the
+    mean of four cells about their shared corner); reflecting walls give zero
+    normal velocity on the wall; periodic corners match their images."""
+    n = 12
+    prm = _prm(n, n - 2, bc=(R, T, P, P))
+    ls = oracle_mod.LevelSet(prm)
+    xc, yc = inputs.centres(prm)
+    Xc, Yc = np.meshgrid(xc, yc)
+    rho = 1.0 + 0.5 * Xc * Yc
+    u, v = 0.25 + 0.5 * Xc - Yc, -0.5 + 0.75 * Xc
+    U = inputs.state_from_primitive(rho, u, v, np.ones_like(rho), 1.4)
+    vel = ls.corner_velocity(U)
+    x, y = inputs.corners(prm)
+    X, Y = np.meshgrid(x, y)
+    inner = (slice(1, -1), slice(1, -1))
+    np.testing.assert_allclose(vel[0][inner], (0.25 + 0.5 * X - Y)[inner], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(vel[1][inner], (-0.5 + 0.75 * X)[inner], rtol=0, atol=1e-15)
+    assert np.all(vel[0][:, 0] == 0.0)                      # reflecting x-low wall
+    np.testing.assert_allclose(vel[0][:, -1][1:-1], (0.5 * (u[:-1, -1] + u[1:, -1]))[:], atol=1e-15)
+    assert np.array_equal(vel[:, 0, :], vel[:, -1, :])    # periodic in y

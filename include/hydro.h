@@ -51,6 +51,7 @@ enum {
 enum { HYDRO_PERIODIC = 0, HYDRO_TRANSMISSIVE = 1, HYDRO_REFLECTING = 2 };
 enum { HYDRO_CARTESIAN = 0, HYDRO_CYLINDRICAL = 1 };
 enum { HYDRO_FP64 = 0, HYDRO_FP32_BULK = 1 };
+enum { HYDRO_COMPONENTWISE = 0, HYDRO_CHARACTERISTIC = 1 };
 
 /* Problem description (Sect. 2.1, Eq. euler2D).
  *  nx, ny      interior cells; nx >= 3; ny == 1 is the 1D limit (no y sweep,
@@ -74,7 +75,15 @@ enum { HYDRO_FP64 = 0, HYDRO_FP32_BULK = 1 };
  *  p_floor     minimum density): a cell with rho < rho_floor becomes
  *              (rho_floor, 0, 0, p_floor / (gamma - 1)); then a cell with
  *              p < p_floor gets E = p_floor / (gamma - 1) + m.v / 2 (rho and m
- *              kept).  p_floor must then be > 0.  rho_floor <= 0 disables both. */
+ *              kept).  p_floor must then be > 0.  rho_floor <= 0 disables both.
+ *  reconstruction  HYDRO_COMPONENTWISE: WENO5 on each component of the split
+ *              fluxes (what Sect. 2.1 describes).  HYDRO_CHARACTERISTIC: the
+ *              split fluxes projected, per face, on the left eigenvectors of
+ *              the flux Jacobian at the Roe average of the two cells beside
+ *              the face, reconstructed field by field and mapped back (the
+ *              scheme's name in Sect. 2.1, "WENO-Roe"); FP64 only, no adjoint
+ *              (hydro_step_vjp* return HYDRO_E_INVALID); a face whose averaged
+ *              sound speed is not real counts as an unphysical state. */
 typedef struct {
   int32_t nx, ny;
   double xlo, xhi, ylo, yhi;
@@ -84,6 +93,7 @@ typedef struct {
   int32_t precision;
   double gx, gy;
   double rho_floor, p_floor;
+  int32_t reconstruction;
 } hydro_params;
 
 /* Global Lax-Friedrichs speeds of the three Runge-Kutta stages (Sect. 2.1:
@@ -165,6 +175,75 @@ int hydro_step_save(hydro_ctx* ctx, const double* U_in, double* U_out, double dt
 int hydro_step_vjp_saved(hydro_ctx* ctx, const double* U_n, const double* U1, const double* U2,
                          double dt, const hydro_alpha* alpha, const double* lam_next,
                          double* lam_prev);
+
+/* Gravitational potential of a density field (Sect. 2.1): the Poisson
+ * equation (1/r) d/dr (r dPhi/dr) + d^2Phi/dz^2 = 4 pi G rho on the context's
+ * quarter plane (cylindrical geometry with xlo = ylo = 0: x = r, y = z),
+ * solved by successive over-relaxation (factor omega in (0, 2)) of
+ * Gauss-Seidel sweeps in red-black order (colour (i + j) mod 2, red first),
+ * stopped after the first iteration whose largest relative change
+ * |new - old| / |new| is below tol (the paper uses 1e-8), or after max_iter.
+ * Reflecting at the axis and the symmetry plane; the outer ghost cells hold
+ * the Roche value -G mass / sqrt(r^2 + z^2) (mass: the total mass of the
+ * mirror-symmetric configuration, given by the caller).  Cell-centred
+ * five-point stencil, r-operator in flux form.
+ *  rho       device [ny][nx] (the density component of a state will do).
+ *  phi       device [ny][nx], in: starting potential; out: the solution.
+ *  iters_out, change_out: NULL or receive the iterations done and the last
+ *            iteration's largest relative change (not converged when
+ *            iters == max_iter and change >= tol).
+ * Synchronises once per batch of iterations (batches of 8, 16, .. 256).
+ * INVALID if the context is not such a quarter plane. */
+int hydro_poisson(hydro_ctx* ctx, const double* rho, double* phi, double G, double mass,
+                  double omega, double tol, int32_t max_iter, int32_t* iters_out,
+                  double* change_out);
+
+/* g = -grad Phi at the cell centres by central differences (mirror across the
+ * axis and the plane, Roche values beyond the outer edges), for use as the
+ * gravity field of hydro_create.  g_out: device [2][ny][nx] (g_r, g_z).
+ * Same geometry requirement as hydro_poisson.  Asynchronous. */
+int hydro_gravity(hydro_ctx* ctx, const double* phi, double G, double mass, double* g_out);
+
+/* ---- Level set (Sect. 2.3): the flame front as the zero contour of a field S
+ * on the grid corners (S > 0 burnt, S < 0 fuel).  Corner (i, j), i = 0..nx,
+ * j = 0..ny, lies at (xlo + i dx, ylo + j dy); corner fields are device arrays
+ * [ny+1][nx+1], corner velocities [2][ny+1][nx+1] (u, v).  Ghost corners follow
+ * the context's boundary codes: periodic (corner nx is corner 0's image),
+ * reflecting (mirror about the wall corner), transmissive (linear
+ * extrapolation).  Two-dimensional contexts only (ny >= 3), any geometry (the
+ * field is advected in the (x, y) plane).  The first level-set call allocates
+ * two corner fields and room for 3 front points per corner (HYDRO_E_NOMEM when
+ * that fails).  All four calls run on the context's stream. */
+
+/* Corner velocity from a cell state U[4][ny][nx]: the mean of the velocities
+ * m/rho of the four cells that share the corner, with the fluid's ghost cells
+ * beyond the grid.  Asynchronous. */
+int hydro_ls_velocity(hydro_ctx* ctx, const double* U, double* vel);
+
+/* One SSP-RK3 step of dS/dt = -(v + v_flame) . grad S, v_flame = s_flame along
+ * the outward normal of the burnt region, i.e. S_t + u S_x + v S_y =
+ * s_flame |grad S|: Hamilton-Jacobi WENO5 (the fluid's reconstruction applied
+ * to one-sided differences), global Lax-Friedrichs flux with speeds
+ * max|u| + s_flame, max|v| + s_flame over the corners, velocity frozen over
+ * the step, time step dt.  S in place (periodic image corners are set from
+ * their sources first).  s_flame >= 0.  Asynchronous. */
+int hydro_ls_step(hydro_ctx* ctx, double* S, const double* vel, double s_flame, double dt);
+
+/* Front points of S: one where neighbouring corners (in x or in y) have values
+ * of opposite sign, placed by linear interpolation, and one at every corner
+ * where S = 0.  pts: device [cap][2] (x, y), filled in no particular order with
+ * min(count, cap) points; *count receives the number found.  Synchronises. */
+int hydro_ls_front(hydro_ctx* ctx, const double* S, double* pts, int64_t cap, int64_t* count);
+
+/* Re-distancing: every corner takes d, its distance to the nearest front point,
+ * and S = H(d) S + (1 - H(d)) sign(S) d with
+ * H(d) = (1 - tanh((d - 3D) / (D/3))) / (1 - tanh(-9)), D = min(dx, dy): values
+ * within about two spacings of the front are kept, far values become the
+ * distance.  With no front point S is left as it is.  dist: NULL or device
+ * [ny+1][nx+1] receiving d (untouched without front points).  *npoints (may be
+ * NULL) receives the number of front points.  Synchronises once (to size the
+ * search), then runs asynchronously. */
+int hydro_ls_redistance(hydro_ctx* ctx, double* S, double* dist, int64_t* npoints);
 
 /* Totals of rho, m_x, m_y, E times the cell volume (dx dy; 2 pi r_i dx dy in
  * cylindrical geometry), with compensated (Neumaier) summation in a fixed

@@ -26,6 +26,8 @@ UNITS = {
     "stage_fp64.hip": ["-ffp-contract=off"],
     "stage_fp32.hip": ["-ffp-contract=fast"],
     "reduce.hip": ["-ffp-contract=off"],
+    "poisson.hip": ["-ffp-contract=off"],
+    "levelset.hip": ["-ffp-contract=off"],
     "vjp_fp64.hip": [],
     "vjp_fp32.hip": [],
 }

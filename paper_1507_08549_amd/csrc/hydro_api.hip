@@ -30,6 +30,16 @@ struct hydro_ctx {
   int nsum;
   hy::Ctl* h_ctl;        // pinned host staging
   double* h_buf;         // pinned host staging ([8])
+  // level set (allocated by the first level-set call)
+  double* ls_a;          // stage corner fields
+  double* ls_b;
+  double* ls_pts;        // front points, capacity 3 per corner ([2] each)
+  hy::LsCtl* ls_ctl;
+  unsigned long long* h_npts;  // pinned host staging
+  // potential solver (allocated by the first call)
+  double* p_scratch;     // second potential buffer
+  hy::PoissonCtl* pc;
+  hy::PoissonCtl* h_pc;  // pinned host staging (header)
 };
 
 namespace {
@@ -67,6 +77,9 @@ int check_params(const hydro_params* p) {
   if (p->geometry == HYDRO_CYLINDRICAL && p->xlo < 0.0) return HYDRO_E_INVALID;
   if (p->precision != HYDRO_FP64 && p->precision != HYDRO_FP32_BULK) return HYDRO_E_INVALID;
   if (p->rho_floor > 0.0 && !(p->p_floor > 0.0)) return HYDRO_E_INVALID;
+  if (p->reconstruction != HYDRO_COMPONENTWISE && p->reconstruction != HYDRO_CHARACTERISTIC)
+    return HYDRO_E_INVALID;
+  if (p->reconstruction == HYDRO_CHARACTERISTIC && p->precision != HYDRO_FP64) return HYDRO_E_INVALID;
   return HYDRO_OK;
 }
 
@@ -98,6 +111,7 @@ hy::Geom make_geom(const hydro_params* p, const double* gravity) {
   double dmin = g.dx;
   if (g.has_y && g.dy < dmin) dmin = g.dy;
   g.cfl_dmin = p->cfl * dmin;
+  g.charw = p->reconstruction == HYDRO_CHARACTERISTIC;
   return g;
 }
 
@@ -214,6 +228,14 @@ void free_ctx(hydro_ctx* c) {
   (void)hipFree(c->apart);
   (void)hipHostFree(c->h_ctl);
   (void)hipHostFree(c->h_buf);
+  (void)hipFree(c->ls_a);
+  (void)hipFree(c->ls_b);
+  (void)hipFree(c->ls_pts);
+  (void)hipFree(c->ls_ctl);
+  (void)hipHostFree(c->h_npts);
+  (void)hipFree(c->p_scratch);
+  (void)hipFree(c->pc);
+  (void)hipHostFree(c->h_pc);
   delete c;
 }
 
@@ -348,7 +370,7 @@ int hydro_step_vjp(hydro_ctx* c, const double* U_n, double dt, const hydro_alpha
                    const double* lam_next, double* lam_prev) {
   if (!c || !U_n || !alpha || !lam_next || !lam_prev) return HYDRO_E_INVALID;
   if (lam_prev == lam_next || lam_prev == U_n || !(dt >= 0.0)) return HYDRO_E_INVALID;
-  if (c->g.floor_on) return HYDRO_E_INVALID;
+  if (c->g.floor_on || c->g.charw) return HYDRO_E_INVALID;
   DeviceGuard dg(c->device);
   if (!dg.ok) return HYDRO_E_DEVICE;
   // Recompute the stage states with the recorded speeds.
@@ -378,10 +400,268 @@ int hydro_step_vjp_saved(hydro_ctx* c, const double* U_n, const double* U1, cons
   if (!c || !U_n || !U1 || !U2 || !alpha || !lam_next || !lam_prev) return HYDRO_E_INVALID;
   if (lam_prev == lam_next || lam_prev == U_n || lam_prev == U1 || lam_prev == U2 || !(dt >= 0.0))
     return HYDRO_E_INVALID;
-  if (c->g.floor_on) return HYDRO_E_INVALID;
+  if (c->g.floor_on || c->g.charw) return HYDRO_E_INVALID;
   DeviceGuard dg(c->device);
   if (!dg.ok) return HYDRO_E_DEVICE;
   return vjp_impl(c, U_n, U1, U2, dt, alpha, lam_next, lam_prev);
+}
+
+namespace {
+hy::PoissonArgs poisson_args(const hydro_ctx* c, const double* rho, double* phi, double G, double mass,
+                             double omega, double tol) {
+  hy::PoissonArgs a{};
+  a.nr = c->p.nx;
+  a.nz = c->p.ny;
+  a.dr = c->g.dx;  // xlo = 0: (xhi - 0) / nx
+  a.dz = c->g.dy;
+  a.idr2 = 1.0 / (a.dr * a.dr);
+  a.idz2 = 1.0 / (a.dz * a.dz);
+  a.four_pi_g = (4.0 * 3.141592653589793) * G;
+  a.G = G;
+  a.mass = mass;
+  a.omega = omega;
+  a.tol = tol;
+  a.rho = rho;
+  a.phi = phi;
+  a.ctl = c->ctl;
+  return a;
+}
+
+bool poisson_geometry_ok(const hydro_ctx* c) {
+  return c->g.cyl && c->g.has_y && c->p.xlo == 0.0 && c->p.ylo == 0.0;
+}
+
+// One launch per colour sweep (the plain order, kept as a cross-check of the
+// blocked solver).
+int poisson_sweeps(hydro_ctx* c, hy::PoissonArgs a, int32_t max_iter, int32_t* iters_out,
+                   double* change_out) {
+  HY_CHECK(hy::launch_poisson_init(c->ctl, c->stream));
+  int k = 0, batch = 8;
+  bool done = false;
+  while (k < max_iter && !done) {
+    const int b = batch < max_iter - k ? batch : max_iter - k;
+    for (int it = k; it < k + b; ++it) {
+      a.iter = it;
+      a.colour = 0;
+      HY_CHECK(hy::launch_poisson_sweep(a, c->stream));
+      a.colour = 1;
+      HY_CHECK(hy::launch_poisson_sweep(a, c->stream));
+    }
+    k += b;
+    a.iter = k;
+    HY_CHECK(hy::launch_poisson_check(a, c->stream));
+    HY_CHECK(hipMemcpyAsync(c->h_ctl, c->ctl, hy::kCtlHeader, hipMemcpyDeviceToHost, c->stream));
+    HY_CHECK(hipStreamSynchronize(c->stream));
+    done = c->h_ctl->pdone != 0;
+    batch = batch < 256 ? 2 * batch : 256;
+  }
+  if (iters_out) *iters_out = done ? c->h_ctl->piters : max_iter;
+  if (change_out) *change_out = c->h_ctl->pchange;
+  return HYDRO_OK;
+}
+
+int ensure_poisson(hydro_ctx* c) {
+  if (c->pc) return HYDRO_OK;
+  hy::PoissonCtl* pc = nullptr;
+  bool ok = hipMalloc(&c->p_scratch, c->n * sizeof(double)) == hipSuccess &&
+            hipMalloc(&pc, sizeof(hy::PoissonCtl)) == hipSuccess &&
+            hipHostMalloc((void**)&c->h_pc, sizeof(hy::PoissonCtl), hipHostMallocDefault) == hipSuccess;
+  if (!ok) {
+    (void)hipFree(c->p_scratch);
+    (void)hipFree(pc);
+    (void)hipHostFree(c->h_pc);
+    c->p_scratch = nullptr;
+    c->h_pc = nullptr;
+    (void)hipGetLastError();
+    return HYDRO_E_NOMEM;
+  }
+  c->pc = pc;
+  return HYDRO_OK;
+}
+
+// Temporally blocked: up to K iterations per launch, launches in batches of
+// 2, 4, .. 64, a check after each batch, one host synchronisation per batch.
+int poisson_blocked(hydro_ctx* c, hy::PoissonArgs a, int32_t max_iter, int32_t* iters_out,
+                    double* change_out) {
+  if (int rc = ensure_poisson(c)) return rc;
+  const bool big = hy::poisson_block_big(a.nr, a.nz);
+  const int K = hy::poisson_block_k(big);
+  a.X[0] = a.phi;
+  a.X[1] = c->p_scratch;
+  a.pc = c->pc;
+  HY_CHECK(hy::launch_poisson_block_init(c->pc, c->stream));
+  int l = 0, t = 0, kprev = 0, batch = 2;
+  for (;;) {
+    for (int b = 0; b < batch && t < max_iter; ++b) {
+      a.l = l;
+      a.kprev = kprev;
+      a.kcur = K < max_iter - t ? K : max_iter - t;
+      a.t0 = t;
+      a.final_ = 0;
+      HY_CHECK(hy::launch_poisson_block(a, big, c->stream));
+      kprev = a.kcur;
+      t += a.kcur;
+      ++l;
+    }
+    // check launch l-1 (and, after the last iteration, record the outcome)
+    a.l = l;
+    a.kprev = kprev;
+    a.kcur = 0;
+    a.t0 = t;
+    a.final_ = t >= max_iter;
+    HY_CHECK(hy::launch_poisson_block(a, big, c->stream));
+    HY_CHECK(hipMemcpyAsync(c->h_pc, c->pc, 32, hipMemcpyDeviceToHost, c->stream));
+    HY_CHECK(hipStreamSynchronize(c->stream));
+    if (c->h_pc->done_launch != 0x7fffffff) break;
+    batch = batch < 64 ? 2 * batch : 64;
+  }
+  if (c->h_pc->result == 1)
+    HY_CHECK(hipMemcpyAsync(a.phi, c->p_scratch, c->n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  if (iters_out) *iters_out = c->h_pc->iters;
+  if (change_out) *change_out = c->h_pc->change;
+  return HYDRO_OK;
+}
+}  // namespace
+
+int hydro_poisson(hydro_ctx* c, const double* rho, double* phi, double G, double mass, double omega,
+                  double tol, int32_t max_iter, int32_t* iters_out, double* change_out) {
+  if (!c || !rho || !phi || !(omega > 0.0 && omega < 2.0) || max_iter < 1 || !(tol >= 0.0))
+    return HYDRO_E_INVALID;
+  if (!poisson_geometry_ok(c) || !(mass > 0.0) || !(G > 0.0)) return HYDRO_E_INVALID;
+  DeviceGuard dg(c->device);
+  if (!dg.ok) return HYDRO_E_DEVICE;
+  hy::PoissonArgs a = poisson_args(c, rho, phi, G, mass, omega, tol);
+  return poisson_blocked(c, a, max_iter, iters_out, change_out);
+}
+
+int hydro_gravity(hydro_ctx* c, const double* phi, double G, double mass, double* g_out) {
+  if (!c || !phi || !g_out || !poisson_geometry_ok(c) || !(mass > 0.0) || !(G > 0.0))
+    return HYDRO_E_INVALID;
+  DeviceGuard dg(c->device);
+  if (!dg.ok) return HYDRO_E_DEVICE;
+  hy::PoissonArgs a = poisson_args(c, nullptr, const_cast<double*>(phi), G, mass, 1.0, 0.0);
+  HY_CHECK(hy::launch_gravity(a, g_out, c->stream));
+  return HYDRO_OK;
+}
+
+namespace {
+size_t ls_corners(const hydro_ctx* c) { return (size_t)(c->p.nx + 1) * (size_t)(c->p.ny + 1); }
+
+int ensure_ls(hydro_ctx* c) {
+  if (c->ls_ctl) return HYDRO_OK;
+  const size_t nc = ls_corners(c);
+  bool ok = hipMalloc(&c->ls_a, nc * sizeof(double)) == hipSuccess &&
+            hipMalloc(&c->ls_b, nc * sizeof(double)) == hipSuccess &&
+            hipMalloc(&c->ls_pts, 3 * nc * 2 * sizeof(double)) == hipSuccess &&
+            hipHostMalloc((void**)&c->h_npts, sizeof(unsigned long long), hipHostMallocDefault) == hipSuccess;
+  hy::LsCtl* lc = nullptr;
+  ok = ok && hipMalloc(&lc, sizeof(hy::LsCtl)) == hipSuccess;
+  if (!ok) {
+    (void)hipFree(c->ls_a);
+    (void)hipFree(c->ls_b);
+    (void)hipFree(c->ls_pts);
+    (void)hipFree(lc);
+    (void)hipHostFree(c->h_npts);
+    c->ls_a = c->ls_b = c->ls_pts = nullptr;
+    c->h_npts = nullptr;
+    (void)hipGetLastError();
+    return HYDRO_E_NOMEM;
+  }
+  c->ls_ctl = lc;
+  return HYDRO_OK;
+}
+
+hy::LsArgs ls_args(const hydro_ctx* c) {
+  hy::LsArgs a{};
+  a.mx = c->p.nx + 1;
+  a.my = c->p.ny + 1;
+  for (int k = 0; k < 4; ++k) a.bc[k] = c->p.bc[k];
+  a.xlo = c->p.xlo;
+  a.ylo = c->p.ylo;
+  a.dx = c->g.dx;
+  a.dy = c->g.dy;
+  a.eps = c->p.weno_eps;
+  a.lc = c->ls_ctl;
+  return a;
+}
+
+// Front points of S into the context's buffer; returns their number in *np.
+int ls_front(hydro_ctx* c, const double* S, long long* np) {
+  hy::LsArgs a = ls_args(c);
+  a.V = S;
+  HY_CHECK(hy::launch_ls_front(a, c->ls_pts, c->stream));
+  HY_CHECK(hipMemcpyAsync(c->h_npts, &c->ls_ctl->npts, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                          c->stream));
+  HY_CHECK(hipStreamSynchronize(c->stream));
+  *np = (long long)*c->h_npts;
+  return HYDRO_OK;
+}
+}  // namespace
+
+#define HY_LS_PROLOGUE(c)                       \
+  if (!(c)) return HYDRO_E_INVALID;             \
+  if ((c)->p.ny < 3) return HYDRO_E_INVALID;    \
+  DeviceGuard dg((c)->device);                  \
+  if (!dg.ok) return HYDRO_E_DEVICE;            \
+  if (int rc_ = ensure_ls(c)) return rc_
+
+int hydro_ls_velocity(hydro_ctx* c, const double* U, double* vel) {
+  HY_LS_PROLOGUE(c);
+  if (!U || !vel) return HYDRO_E_INVALID;
+  hy::LsArgs a = ls_args(c);
+  a.W = vel;
+  HY_CHECK(hy::launch_ls_velocity(a, U, c->stream));
+  return HYDRO_OK;
+}
+
+int hydro_ls_step(hydro_ctx* c, double* S, const double* vel, double s_flame, double dt) {
+  HY_LS_PROLOGUE(c);
+  if (!S || !vel || !(s_flame >= 0.0) || !std::isfinite(s_flame) || !std::isfinite(dt))
+    return HYDRO_E_INVALID;
+  hy::LsArgs a = ls_args(c);
+  a.vel = vel;
+  a.s_f = s_flame;
+  a.dt = dt;
+  a.S0 = S;
+  HY_CHECK(hy::launch_ls_images(a, S, c->stream));
+  HY_CHECK(hy::launch_ls_alpha(a, c->stream));
+  const double b[3] = {1.0, 0.25, 2.0 / 3.0};
+  const double* in[3] = {S, c->ls_a, c->ls_b};
+  double* out[3] = {c->ls_a, c->ls_b, S};
+  for (int st = 0; st < 3; ++st) {
+    a.V = in[st];
+    a.W = out[st];
+    a.b = b[st];
+    HY_CHECK(hy::launch_ls_stage(a, c->stream));
+  }
+  return HYDRO_OK;
+}
+
+int hydro_ls_front(hydro_ctx* c, const double* S, double* pts, int64_t cap, int64_t* count) {
+  HY_LS_PROLOGUE(c);
+  if (!S || (cap > 0 && !pts) || cap < 0) return HYDRO_E_INVALID;
+  long long np = 0;
+  if (int rc = ls_front(c, S, &np)) return rc;
+  const long long m = np < cap ? np : cap;
+  if (m > 0)
+    HY_CHECK(hipMemcpyAsync(pts, c->ls_pts, (size_t)m * 2 * sizeof(double), hipMemcpyDeviceToDevice,
+                            c->stream));
+  if (count) *count = np;
+  return HYDRO_OK;
+}
+
+int hydro_ls_redistance(hydro_ctx* c, double* S, double* dist, int64_t* npoints) {
+  HY_LS_PROLOGUE(c);
+  if (!S) return HYDRO_E_INVALID;
+  long long np = 0;
+  if (int rc = ls_front(c, S, &np)) return rc;
+  if (np > 0) {
+    hy::LsArgs a = ls_args(c);
+    a.W = S;
+    HY_CHECK(hy::launch_ls_distance(a, c->ls_pts, dist, c->stream));
+  }
+  if (npoints) *npoints = np;
+  return HYDRO_OK;
 }
 
 int hydro_sums(hydro_ctx* c, const double* U, double out_host[4]) {

@@ -29,6 +29,7 @@ struct Geom {
   int floor_on;
   double rho_floor, p_floor, e_floor;  // e_floor = p_floor / (gamma - 1)
   double cfl_dmin;       // cfl * min(dx, dy) (dx in 1D)
+  int charw;             // characteristic-wise reconstruction (FP64 only)
 };
 
 // Device-resident control block of a context.
@@ -44,13 +45,17 @@ struct Geom {
 // over the sub-slots (one wavefront, NSUB = 64 lanes).
 constexpr int NSUB = 64;
 struct Ctl {
-  double dt;     // time step of the current step (device-computed mode)
-  double t;      // time reached
-  int active;    // current step is taken (t < t_end)
-  int steps;     // steps taken by hydro_run
-  int flag;      // sticky: a stage produced rho <= 0 or p <= 0
-  int pad[9];
+  double dt;       // time step of the current step (device-computed mode)
+  double t;        // time reached
+  double pchange;  // potential solver: largest relative change of the last iteration
+  int active;      // current step is taken (t < t_end)
+  int steps;       // steps taken by hydro_run
+  int flag;        // sticky: a stage produced rho <= 0 or p <= 0
+  int pdone;       // potential solver: converged
+  int piters;      // potential solver: iterations done when it converged
+  int pad[5];
   unsigned long long slot[3][NSUB][16];
+  unsigned long long pslot[2][NSUB][16];  // potential solver: max relative change per iteration
 };
 constexpr size_t kCtlHeader = 64;  // bytes before slot[][][]: what the host reads back
 static_assert(offsetof(Ctl, slot) == kCtlHeader, "control header layout");
@@ -84,5 +89,69 @@ hipError_t launch_alpha_reduce(const Geom& g, const double* U, Ctl* ctl, int slo
 hipError_t launch_sums(const Geom& g, const double* U, double* partial, int nblocks, double* out,
                        hipStream_t s);
 int sums_blocks(const Geom& g);
+
+// Potential solver (red-black over-relaxed Gauss-Seidel in (r, z)).
+// Control block of the temporally blocked potential solver.
+constexpr int PKMAX = 4;  // most iterations per launch
+struct PoissonCtl {
+  int done_launch;  // launch that ended the solve (INT_MAX while running)
+  int iters;        // iterations done
+  int result;       // buffer holding the result: 0 the caller's, 1 the scratch
+  int pad0;
+  double change;    // largest relative change of the last iteration
+  double pad1[5];
+  unsigned long long bank[3][PKMAX][NSUB][16];  // per launch (ring of 3), per iteration: max change
+};
+
+struct PoissonArgs {
+  int nr, nz;
+  double dr, dz, idr2, idz2;
+  double four_pi_g, G, mass, omega, tol;
+  const double* rho;
+  double* phi;
+  Ctl* ctl;
+  int iter;    // 0-based iteration index
+  int colour;  // 0 red, 1 black
+  // blocked solver
+  double* X[2];     // potential buffers: the caller's and a scratch one
+  PoissonCtl* pc;
+  int l;            // launch index (buffer parity, bank)
+  int kprev;        // iterations done by launch l-1 (0: none)
+  int kcur;         // iterations for this launch (0: only check launch l-1)
+  int t0;           // index of this launch's first iteration
+  int final_;       // no more launches follow: record the outcome
+};
+hipError_t launch_poisson_block_init(PoissonCtl* pc, hipStream_t s);
+hipError_t launch_poisson_block(const PoissonArgs& a, bool big, hipStream_t s);
+int poisson_block_k(bool big);
+bool poisson_block_big(int nr, int nz);
+hipError_t launch_poisson_init(Ctl* ctl, hipStream_t s);
+hipError_t launch_poisson_sweep(const PoissonArgs& a, hipStream_t s);
+hipError_t launch_poisson_check(const PoissonArgs& a, hipStream_t s);
+hipError_t launch_gravity(const PoissonArgs& a, double* g, hipStream_t s);
+
+// Level set on the corners ([ny+1][nx+1]).
+struct LsCtl {
+  unsigned long long npts;  // front points found
+  unsigned long long pad[15];
+  unsigned long long amax[NSUB][16];  // [sub][0]: max|u|, [sub][1]: max|v| (bit patterns)
+};
+struct LsArgs {
+  int mx, my;          // corners per row / column (nx + 1, ny + 1)
+  int bc[4];           // fluid codes: 0 periodic, 1 transmissive (linear extrapolation), 2 reflecting
+  double xlo, ylo, dx, dy, eps;
+  double s_f, dt, b;   // flame speed, time step, stage weight
+  const double* S0;    // step input
+  const double* V;     // stage input (front search: the field)
+  double* W;           // stage output (distance: the field, in place; velocity: the output)
+  const double* vel;   // corner velocity [2][my][mx]
+  LsCtl* lc;
+};
+hipError_t launch_ls_alpha(const LsArgs& a, hipStream_t s);
+hipError_t launch_ls_images(const LsArgs& a, double* S, hipStream_t s);
+hipError_t launch_ls_stage(const LsArgs& a, hipStream_t s);
+hipError_t launch_ls_front(const LsArgs& a, double* pts, hipStream_t s);
+hipError_t launch_ls_distance(const LsArgs& a, const double* pts, double* dist, hipStream_t s);
+hipError_t launch_ls_velocity(const LsArgs& a, const double* U, hipStream_t s);
 
 }  // namespace hy

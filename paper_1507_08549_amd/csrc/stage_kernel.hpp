@@ -8,7 +8,8 @@
 //   1. primitive variables and the globally Lax-Friedrichs split fluxes
 //      f+- = (F(U) +- alpha_x U) / 2 of every x-point (Sect. 2.1),
 //   2. WENO5 reconstruction at every x-face of the tile, one (face, component)
-//      per work item: F^ = W(f+ upwind-left) + W(f- upwind-right),
+//      per work item: F^ = W(f+ upwind-left) + W(f- upwind-right); with the
+//      characteristic option one whole face per work item (char_face),
 //   3. the same in y with alpha_y (skipped in the 1D limit),
 //   4. per cell: divergence, sources of Eq. euler2D (gravity, cylindrical
 //      geometric terms), the SSP-RK3 stage combination in FP64, the optional
@@ -27,6 +28,7 @@
 #pragma once
 
 #include "hydro_internal.hpp"
+#include "ieee.hpp"
 
 namespace hy {
 
@@ -63,12 +65,12 @@ template <typename R> struct Prim { R u, v, p, c; };
 __device__ __forceinline__ Prim<double> prim(double r, double mx, double my, double E,
                                              double gamma, double gm1) {
   Prim<double> w;
-  double rinv = 1.0 / r;
+  double rinv = cr_div(1.0, r);
   w.u = mx * rinv;
   w.v = my * rinv;
   double ke2 = mx * w.u + my * w.v;
   w.p = gm1 * (E - 0.5 * ke2);
-  w.c = __builtin_sqrt((gamma * w.p) * rinv);
+  w.c = cr_sqrt((gamma * w.p) * rinv);
   return w;
 }
 
@@ -97,7 +99,7 @@ __device__ __forceinline__ double weno5(double v0, double v1, double v2, double 
   double w2 = 3.0 * (s0 * s1);
   double num = __builtin_fma(w2, p2, __builtin_fma(w1, p1, w0 * p0));
   double den = 6.0 * ((w0 + w1) + w2);
-  return num / den;
+  return cr_div(num, den);
 }
 
 __device__ __forceinline__ double lf_fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
@@ -166,6 +168,73 @@ __device__ __forceinline__ void split_flux(const R U[4], R gamma, R gm1, R alpha
   }
 }
 
+// ------------------------------------------- characteristic-wise faces (FP64)
+
+__device__ __forceinline__ double dot4(double a0, double a1, double a2, double a3, const double b[4]) {
+  return __builtin_fma(a3, b[3], __builtin_fma(a2, b[2], __builtin_fma(a1, b[1], a0 * b[0])));
+}
+
+// Face value between stencil points 2 and 3 of a line whose points sit at
+// base + k * st (k = 0..5) in LDS: F = split fluxes [8][np] (f+ then f-,
+// components rho, m_x, m_y, E), Q = [4][np] per point sqrt(rho), u, v,
+// H = (E + p)/rho.  The split fluxes are projected on the left eigenvectors of
+// the flux Jacobian at the Roe average of points 2 and 3, in the frame
+// (rho, m_n, m_t, E) (n = x for DIR 0, y for DIR 1), reconstructed field by
+// field, and mapped back with the right eigenvectors.  The oracle's
+// operations in the oracle's order.  Returns false when the averaged sound
+// speed is not real.
+template <int DIR>
+__device__ __forceinline__ bool char_face(const double* F, const double* Q, int np, int base, int st,
+                                          double gm1, double eps, double out[4]) {
+  constexpr int CN = DIR == 0 ? 1 : 2, CT = DIR == 0 ? 2 : 1;
+  const int il = base + 2 * st, ir = base + 3 * st;
+  const double sl = Q[il], sr = Q[ir];
+  const double nl = Q[(1 + DIR) * np + il], nr = Q[(1 + DIR) * np + ir];
+  const double tl = Q[(2 - DIR) * np + il], tr = Q[(2 - DIR) * np + ir];
+  const double Hl = Q[3 * np + il], Hr = Q[3 * np + ir];
+  const double den = sl + sr;
+  const double un = cr_div(sl * nl + sr * nr, den);
+  const double ut = cr_div(sl * tl + sr * tr, den);
+  const double H = cr_div(sl * Hl + sr * Hr, den);
+  const double q2 = un * un + ut * ut;
+  const double c2 = gm1 * (H - 0.5 * q2);
+  const bool ok = c2 > 0.0 && __builtin_isfinite(c2);
+  const double c = cr_sqrt(c2), ic = cr_div(1.0, c);
+  const double b1 = cr_div(gm1, c2), b2 = (0.5 * q2) * b1;
+  double gh[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    double l0, l1, l2, l3;
+    if (m == 0) { l0 = 0.5 * (b2 + un * ic); l1 = 0.5 * (-(b1 * un) - ic); l2 = -0.5 * (b1 * ut); l3 = 0.5 * b1; }
+    else if (m == 1) { l0 = 1.0 - b2; l1 = b1 * un; l2 = b1 * ut; l3 = -b1; }
+    else if (m == 2) { l0 = -ut; l1 = 0.0; l2 = 1.0; l3 = 0.0; }
+    else { l0 = 0.5 * (b2 - un * ic); l1 = 0.5 * (ic - b1 * un); l2 = -0.5 * (b1 * ut); l3 = 0.5 * b1; }
+    double g[6], h[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const int p = base + k * st;
+      if (k < 5) {
+        const double f[4] = {F[p], F[CN * np + p], F[CT * np + p], F[3 * np + p]};
+        g[k] = dot4(l0, l1, l2, l3, f);
+      }
+      if (k > 0) {
+        const double f[4] = {F[4 * np + p], F[(4 + CN) * np + p], F[(4 + CT) * np + p], F[7 * np + p]};
+        h[k] = dot4(l0, l1, l2, l3, f);
+      }
+    }
+    gh[m] = weno5(g[0], g[1], g[2], g[3], g[4], eps) + weno5(h[5], h[4], h[3], h[2], h[1], eps);
+  }
+  const double r0 = dot4(1.0, 1.0, 0.0, 1.0, gh);
+  const double r1 = dot4(un - c, un, 0.0, un + c, gh);
+  const double r2 = dot4(ut, ut, 1.0, ut, gh);
+  const double r3 = dot4(H - un * c, 0.5 * q2, ut, H + un * c, gh);
+  out[0] = r0;
+  out[CN] = r1;
+  out[CT] = r2;
+  out[3] = r3;
+  return ok;
+}
+
 // Max over the NSUB sub-slots of ring slot s, by wavefront 0, broadcast to the
 // block through LDS.  Every work item of the block must call it.
 __device__ __forceinline__ void read_slot(const Ctl* ctl, int s, double out[3], double* sh) {
@@ -198,7 +267,17 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
   return (b % 8) * (nb / 8) + b / 8;
 }
 
-template <typename R, int TX, int TY, bool HASY>
+// Per-point inputs of the Roe average: sqrt(rho), u, v, H = (E + p)/rho.
+template <typename R>
+__device__ __forceinline__ void store_roe_inputs(const R U[4], R gamma, R gm1, R* Q, int np, int k) {
+  const Prim<R> w = prim(U[0], U[1], U[2], U[3], gamma, gm1);
+  Q[k] = cr_sqrt(U[0]);
+  Q[np + k] = w.u;
+  Q[2 * np + k] = w.v;
+  Q[3 * np + k] = cr_div(U[3] + w.p, U[0]);
+}
+
+template <typename R, int TX, int TY, bool HASY, bool CHAR = false>
 __global__ __launch_bounds__(TX* TY) void stage_kernel(StageArgs a) {
   constexpr int NT = TX * TY;
   constexpr int GY = HASY ? NG : 0;
@@ -214,7 +293,11 @@ __global__ __launch_bounds__(TX* TY) void stage_kernel(StageArgs a) {
   static_assert(NT % 64 == 0, "whole wavefronts");
 
   static_assert(8 * NP >= 4 * NF, "face values fit in the split-flux storage");
-  __shared__ R sF[8][NP];
+  static_assert(!CHAR || sizeof(R) == 8, "characteristic faces are FP64 only");
+  // split fluxes (f+ in 0..3, f- in 4..7); characteristic faces add per point
+  // sqrt(rho), u, v, H (8..11)
+  __shared__ R sF[CHAR ? 12 : 8][NP];
+  bool fbad = false;
   __shared__ double sRed[NW][3];
 
   const Geom& g = a.g;
@@ -235,7 +318,7 @@ __global__ __launch_bounds__(TX* TY) void stage_kernel(StageArgs a) {
     if (a.stage == 0) {
       double t = ctl->t;
       active = !(a.t_end > 0.0) || (t < a.t_end);
-      dt = g.cfl_dmin / sp[2];
+      dt = cr_div(g.cfl_dmin, sp[2]);
       if (a.t_end > 0.0 && t + dt > a.t_end) dt = a.t_end - t;
       if (lead) {
         ctl->active = active ? 1 : 0;
@@ -295,8 +378,9 @@ __global__ __launch_bounds__(TX* TY) void stage_kernel(StageArgs a) {
 
   // ---- 1. x sweep: split fluxes of the tile rows and their x-halo points
   // (read straight from L2 into registers; only the split fluxes live in LDS),
-  // then one (face, component) per work item, face values parked in registers
-  // until every stencil read is done, then written over the split fluxes.
+  // then one (face, component) per work item (a whole face for the
+  // characteristic option), face values parked in registers until every
+  // stencil read is done, then written over the split fluxes.
   {
     const R al = (R)ax;
     for (int k = tid; k < NPX; k += NT) {
@@ -310,28 +394,48 @@ __global__ __launch_bounds__(TX* TY) void stage_kernel(StageArgs a) {
         sF[c][k] = fp[c];
         sF[4 + c][k] = fm[c];
       }
+      if constexpr (CHAR) store_roe_inputs(U, gamma, gm1, &sF[8][0], NP, k);
     }
     __syncthreads();
-    constexpr int KX = (4 * NFX + NT - 1) / NT;
-    R fh[KX];
-#pragma unroll
-    for (int kk = 0; kk < KX; ++kk) {
-      const int t = tid + kk * NT;  // t = (c * TY + j) * (TX + 1) + f
-      if (t < 4 * NFX) {
-        const int f = t % (TX + 1);
-        const int rest = t / (TX + 1);
-        const int j = rest % TY, c = rest / TY;
-        const R* P = &sF[c][j * TXP + f];
-        const R* M = &sF[4 + c][j * TXP + f];
-        fh[kk] = weno5(P[0], P[1], P[2], P[3], P[4], eps) + weno5(M[5], M[4], M[3], M[2], M[1], eps);
-      }
-    }
-    __syncthreads();
+    // faces: work item (tx, ty) takes face tx of row ty for all four
+    // components; the last face of every row (f = TX) is split into 4 * TY
+    // single-component tasks for the first work items.
     R* sFh = &sF[0][0];  // [4][TY][TX + 1], reusing the split-flux storage
+    if constexpr (CHAR) {
+      // one whole face per work item; the last face of every row for the first TY
+      R fh[4], fe[4];
+      fbad |= !char_face<0>(&sF[0][0], &sF[8][0], NP, ty * TXP + tx, 1, g.gm1, g.eps, fh);
+      const bool extra = tid < TY;
+      if (extra) fbad |= !char_face<0>(&sF[0][0], &sF[8][0], NP, tid * TXP + TX, 1, g.gm1, g.eps, fe);
+      __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < KX; ++kk) {
-      const int t = tid + kk * NT;
-      if (t < 4 * NFX) sFh[t] = fh[kk];
+      for (int c = 0; c < 4; ++c) sFh[c * NFX + ty * (TX + 1) + tx] = fh[c];
+      if (extra) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sFh[c * NFX + tid * (TX + 1) + TX] = fe[c];
+      }
+    } else {
+      // one (face, component) per work item
+      constexpr int KX = (4 * NFX + NT - 1) / NT;
+      R fh[KX];
+#pragma unroll
+      for (int kk = 0; kk < KX; ++kk) {
+        const int t = tid + kk * NT;  // t = (c * TY + j) * (TX + 1) + f
+        if (t < 4 * NFX) {
+          const int f = t % (TX + 1);
+          const int rest = t / (TX + 1);
+          const int j = rest % TY, c = rest / TY;
+          const R* P = &sF[c][j * TXP + f];
+          const R* M = &sF[4 + c][j * TXP + f];
+          fh[kk] = weno5(P[0], P[1], P[2], P[3], P[4], eps) + weno5(M[5], M[4], M[3], M[2], M[1], eps);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < KX; ++kk) {
+        const int t = tid + kk * NT;
+        if (t < 4 * NFX) sFh[t] = fh[kk];
+      }
     }
     __syncthreads();
     const R idx = (R)g.idx;
@@ -356,29 +460,47 @@ __global__ __launch_bounds__(TX* TY) void stage_kernel(StageArgs a) {
         sF[c][k] = fp[c];
         sF[4 + c][k] = fm[c];
       }
+      if constexpr (CHAR) store_roe_inputs(U, gamma, gm1, &sF[8][0], NP, k);
     }
     __syncthreads();
-    constexpr int KY = HASY ? (4 * NFY + NT - 1) / NT : 1;
-    R fh[KY];
-#pragma unroll
-    for (int kk = 0; kk < KY; ++kk) {
-      const int t = tid + kk * NT;  // t = (c * (TY + 1) + f) * TX + i
-      if (t < 4 * NFY) {
-        const int i = t % TX;
-        const int rest = t / TX;
-        const int f = rest % (TY + 1), c = rest / (TY + 1);
-        const R* P = &sF[c][f * TX + i];
-        const R* M = &sF[4 + c][f * TX + i];
-        fh[kk] = weno5(P[0], P[TX], P[2 * TX], P[3 * TX], P[4 * TX], eps) +
-                 weno5(M[5 * TX], M[4 * TX], M[3 * TX], M[2 * TX], M[TX], eps);
-      }
-    }
-    __syncthreads();
+    // faces: work item (tx, ty) takes face ty of column tx for all four
+    // components; the last face of every column (f = TY) is split into 4 * TX
+    // single-component tasks.
     R* sFh = &sF[0][0];  // [4][TY + 1][TX]
+    if constexpr (CHAR) {
+      R fh[4], fe[4];
+      fbad |= !char_face<1>(&sF[0][0], &sF[8][0], NP, ty * TX + tx, TX, g.gm1, g.eps, fh);
+      const bool extra = tid < TX;
+      if (extra) fbad |= !char_face<1>(&sF[0][0], &sF[8][0], NP, TY * TX + tid, TX, g.gm1, g.eps, fe);
+      __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < KY; ++kk) {
-      const int t = tid + kk * NT;
-      if (t < 4 * NFY) sFh[t] = fh[kk];
+      for (int c = 0; c < 4; ++c) sFh[c * NFY + ty * TX + tx] = fh[c];
+      if (extra) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sFh[c * NFY + TY * TX + tid] = fe[c];
+      }
+    } else {
+      constexpr int KY = HASY ? (4 * NFY + NT - 1) / NT : 1;
+      R fh[KY];
+#pragma unroll
+      for (int kk = 0; kk < KY; ++kk) {
+        const int t = tid + kk * NT;  // t = (c * (TY + 1) + f) * TX + i
+        if (t < 4 * NFY) {
+          const int i = t % TX;
+          const int rest = t / TX;
+          const int f = rest % (TY + 1), c = rest / (TY + 1);
+          const R* P = &sF[c][f * TX + i];
+          const R* M = &sF[4 + c][f * TX + i];
+          fh[kk] = weno5(P[0], P[TX], P[2 * TX], P[3 * TX], P[4 * TX], eps) +
+                   weno5(M[5 * TX], M[4 * TX], M[3 * TX], M[2 * TX], M[TX], eps);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < KY; ++kk) {
+        const int t = tid + kk * NT;
+        if (t < 4 * NFY) sFh[t] = fh[kk];
+      }
     }
     __syncthreads();
     const R idy = (R)g.idy;
@@ -408,7 +530,7 @@ __global__ __launch_bounds__(TX* TY) void stage_kernel(StageArgs a) {
     if (g.cyl) {
       const Prim<R> w = prim(r, mx, my, E, gamma, gm1);
       const double ri = g.xlo + ((double)I + 0.5) * g.dx;
-      const R ir = (R)(1.0 / ri);
+      const R ir = (R)cr_div(1.0, ri);
       S[0] = S[0] - ir * mx;
       S[1] = S[1] - ir * (mx * w.u);
       S[2] = S[2] - ir * (my * w.u);
@@ -446,7 +568,14 @@ __global__ __launch_bounds__(TX* TY) void stage_kernel(StageArgs a) {
       smax = pw.c + (__builtin_fabs(pw.u) + __builtin_fabs(pw.v));
     }
   }
-  if (a.rhs_only) return;
+  bad = bad || fbad;
+  if (a.rhs_only) {
+    if constexpr (CHAR) {
+      const int anyb = __syncthreads_or(bad ? 1 : 0);
+      if (tid == 0 && anyb) atomicOr(&ctl->flag, 1);
+    }
+    return;
+  }
   if (a.frozen) {  // a replay of recorded speeds needs no new maxima, only the check
     const int anybad = __syncthreads_or(bad ? 1 : 0);
     if (tid == 0 && anybad) atomicOr(&ctl->flag, 1);
@@ -483,18 +612,26 @@ __global__ __launch_bounds__(TX* TY) void stage_kernel(StageArgs a) {
 }
 
 // Tile shapes: 16 x 16 cells (256 work items) in 2D; 256 x 1 in the 1D limit.
-template <typename R>
-hipError_t launch_stage(const StageArgs& a, hipStream_t s) {
+template <typename R, bool CHAR>
+hipError_t launch_stage_variant(const StageArgs& a, hipStream_t s) {
   if (a.g.has_y) {
     constexpr int TX = 16, TY = 16;
     const int nb = ((a.g.nx + TX - 1) / TX) * ((a.g.ny + TY - 1) / TY);
-    hipLaunchKernelGGL((stage_kernel<R, TX, TY, true>), dim3(nb), dim3(TX * TY), 0, s, a);
+    hipLaunchKernelGGL((stage_kernel<R, TX, TY, true, CHAR>), dim3(nb), dim3(TX * TY), 0, s, a);
   } else {
     constexpr int TX = 256, TY = 1;
     const int nb = (a.g.nx + TX - 1) / TX;
-    hipLaunchKernelGGL((stage_kernel<R, TX, TY, false>), dim3(nb), dim3(TX * TY), 0, s, a);
+    hipLaunchKernelGGL((stage_kernel<R, TX, TY, false, CHAR>), dim3(nb), dim3(TX * TY), 0, s, a);
   }
   return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_stage(const StageArgs& a, hipStream_t s) {
+  if constexpr (sizeof(R) == 8) {
+    if (a.g.charw) return launch_stage_variant<R, true>(a, s);
+  }
+  return launch_stage_variant<R, false>(a, s);
 }
 
 }  // namespace hy

@@ -22,6 +22,7 @@ HYDRO_OK, HYDRO_E_INVALID, HYDRO_E_NOMEM, HYDRO_E_DEVICE, HYDRO_E_UNPHYSICAL, HY
 PERIODIC, TRANSMISSIVE, REFLECTING = 0, 1, 2
 CARTESIAN, CYLINDRICAL = 0, 1
 FP64, FP32_BULK = 0, 1
+COMPONENTWISE, CHARACTERISTIC = 0, 1
 
 
 class HydroError(RuntimeError):
@@ -45,6 +46,7 @@ class Params(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("gx", ctypes.c_double), ("gy", ctypes.c_double),
         ("rho_floor", ctypes.c_double), ("p_floor", ctypes.c_double),
+        ("reconstruction", ctypes.c_int32),
     ]
 
 
@@ -57,7 +59,8 @@ _lib = None
 #: names of the entry points declared in include/hydro.h
 ENTRY_POINTS = ("hydro_create", "hydro_destroy", "hydro_cfl", "hydro_step", "hydro_run",
                 "hydro_rhs", "hydro_step_vjp", "hydro_step_save", "hydro_step_vjp_saved",
-                "hydro_sums", "hydro_check", "hydro_strerror")
+                "hydro_poisson", "hydro_gravity", "hydro_ls_velocity", "hydro_ls_step", "hydro_ls_front",
+                "hydro_ls_redistance", "hydro_sums", "hydro_check", "hydro_strerror")
 
 
 def declared_entry_points(header: str = HEADER):
@@ -85,6 +88,14 @@ def load():
     lib.hydro_step_vjp.argtypes = [vp, vp, ctypes.c_double, ctypes.POINTER(Alpha), vp, vp]
     lib.hydro_step_save.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.POINTER(Alpha), vp, vp]
     lib.hydro_step_vjp_saved.argtypes = [vp, vp, vp, vp, ctypes.c_double, ctypes.POINTER(Alpha), vp, vp]
+    lib.hydro_poisson.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), dp]
+    lib.hydro_gravity.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double, vp]
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    lib.hydro_ls_velocity.argtypes = [vp, vp, vp]
+    lib.hydro_ls_step.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_double]
+    lib.hydro_ls_front.argtypes = [vp, vp, vp, ctypes.c_int64, i64p]
+    lib.hydro_ls_redistance.argtypes = [vp, vp, vp, i64p]
     lib.hydro_sums.argtypes = [vp, vp, dp]
     lib.hydro_check.argtypes = [vp]
     lib.hydro_strerror.argtypes = [ip]
@@ -110,6 +121,7 @@ def make_params(prm: dict, precision=FP64) -> Params:
     p.gx, p.gy = float(prm.get("gx", 0.0)), float(prm.get("gy", 0.0))
     p.rho_floor = float(prm.get("rho_floor", 0.0))
     p.p_floor = float(prm.get("p_floor", 0.0))
+    p.reconstruction = int(prm.get("recon", COMPONENTWISE))
     return p
 
 
@@ -261,6 +273,77 @@ class Solver:
                                             self._state(lam_prev, "lam_prev"))
         self._check(rc, "hydro_step_vjp_saved")
         return lam_prev
+
+    def _field(self, x, name, ncomp):
+        t = self.torch
+        if not isinstance(x, t.Tensor) or x.dtype != t.float64 or x.device != self.device:
+            raise TypeError(f"{name} must be a float64 tensor on {self.device}")
+        shape = (self.ny, self.nx) if ncomp == 1 else (ncomp, self.ny, self.nx)
+        if tuple(x.shape) != shape or not x.is_contiguous():
+            raise ValueError(f"{name} must be contiguous with shape {shape}")
+        return x.data_ptr()
+
+    def poisson(self, rho, phi, G, mass, omega=1.9, tol=1e-8, max_iter=100000):
+        """Potential of rho ((ny, nx)) into phi ((ny, nx), in: start, out: solution).
+        Returns (iterations, last relative change)."""
+        it = ctypes.c_int32()
+        ch = ctypes.c_double()
+        rc = self._lib.hydro_poisson(self._h, self._field(rho, "rho", 1), self._field(phi, "phi", 1),
+                                     float(G), float(mass), float(omega), float(tol), int(max_iter),
+                                     ctypes.byref(it), ctypes.byref(ch))
+        self._check(rc, "hydro_poisson")
+        return it.value, ch.value
+
+    def gravity_from_potential(self, phi, G, mass, out=None):
+        """-grad phi, (2, ny, nx); ``out`` may be this solver's own gravity field."""
+        g = self.torch.empty((2, self.ny, self.nx), dtype=self.torch.float64, device=self.device) \
+            if out is None else out
+        rc = self._lib.hydro_gravity(self._h, self._field(phi, "phi", 1), float(G), float(mass),
+                                     self._field(g, "g", 2))
+        self._check(rc, "hydro_gravity")
+        return g
+
+    # -- level set on the (ny+1, nx+1) corners
+    def _corner(self, x, name, ncomp=1):
+        t = self.torch
+        if not isinstance(x, t.Tensor) or x.dtype != t.float64 or x.device != self.device:
+            raise TypeError(f"{name} must be a float64 tensor on {self.device}")
+        shape = (self.ny + 1, self.nx + 1) if ncomp == 1 else (ncomp, self.ny + 1, self.nx + 1)
+        if tuple(x.shape) != shape or not x.is_contiguous():
+            raise ValueError(f"{name} must be contiguous with shape {shape}")
+        return x.data_ptr()
+
+    def ls_velocity(self, U, out=None):
+        """Corner velocity (2, ny+1, nx+1) from a cell state."""
+        vel = self.torch.empty((2, self.ny + 1, self.nx + 1), dtype=self.torch.float64,
+                               device=self.device) if out is None else out
+        rc = self._lib.hydro_ls_velocity(self._h, self._state(U), self._corner(vel, "vel", 2))
+        self._check(rc, "hydro_ls_velocity")
+        return vel
+
+    def ls_step(self, S, vel, s_flame, dt):
+        """One SSP-RK3 step of the level-set advection, S in place."""
+        rc = self._lib.hydro_ls_step(self._h, self._corner(S, "S"), self._corner(vel, "vel", 2),
+                                     float(s_flame), float(dt))
+        self._check(rc, "hydro_ls_step")
+
+    def ls_front(self, S, cap=None):
+        """Front points (n, 2) of S, in no particular order."""
+        cap = 3 * (self.nx + 1) * (self.ny + 1) if cap is None else int(cap)
+        pts = self.torch.empty((max(cap, 1), 2), dtype=self.torch.float64, device=self.device)
+        n = ctypes.c_int64()
+        rc = self._lib.hydro_ls_front(self._h, self._corner(S, "S"), pts.data_ptr(), cap, ctypes.byref(n))
+        self._check(rc, "hydro_ls_front")
+        return pts[:min(n.value, cap)]
+
+    def ls_redistance(self, S, dist=None):
+        """Re-distance S in place; returns the number of front points."""
+        n = ctypes.c_int64()
+        rc = self._lib.hydro_ls_redistance(self._h, self._corner(S, "S"),
+                                           None if dist is None else self._corner(dist, "dist"),
+                                           ctypes.byref(n))
+        self._check(rc, "hydro_ls_redistance")
+        return n.value
 
     def sums(self, U):
         out = (ctypes.c_double * 4)()

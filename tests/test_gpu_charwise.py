@@ -1,0 +1,142 @@
+"""GPU parity of the characteristic-wise reconstruction (HYDRO_CHARACTERISTIC:
+split fluxes projected on the eigenvectors of the flux Jacobian at the Roe
+average of each face's two cells, the "WENO-Roe" variant of Sect. 2.1)
+against the FP64 oracle with recon = 1, through the C ABI: bit for bit on
+small grids (every boundary combination, both geometries, grids smaller than
+a tile and ragged ones), the spatial operator, the 1D limit, the shock tube to
+t = 0.2 with the device time step, and the 512^2 shear layer; FP32-bulk and
+the adjoint are refused."""
+import numpy as np
+import pytest
+
+from paper_1507_08549_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+P, T, R = inputs.PERIODIC, inputs.TRANSMISSIVE, inputs.REFLECTING
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available(), "GPU tests need a GPU"
+    return _t
+
+
+@pytest.fixture(scope="module")
+def hydro():
+    from paper_1507_08549_amd import hydro as _h
+    _h.load()
+    return _h
+
+
+def _dev(torch, a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _random_state(ny, nx, seed, gamma=1.4):
+    rng = np.random.default_rng(seed)
+    return inputs.state_from_primitive(1.0 + 0.5 * rng.uniform(0, 1, (ny, nx)),
+                                       0.5 * rng.uniform(-1, 1, (ny, nx)),
+                                       0.5 * rng.uniform(-1, 1, (ny, nx)),
+                                       1.0 + 0.5 * rng.uniform(0, 1, (ny, nx)), gamma)
+
+
+def _same(got, want, what):
+    got = np.asarray(got)
+    if not np.array_equal(got, want):
+        d = np.abs(got - want)
+        k = np.unravel_index(np.argmax(d), d.shape)
+        raise AssertionError(f"{what}: not bitwise equal; max |diff| {d.max():.3e} at {k}")
+
+
+def _char(prm):
+    prm = dict(prm)
+    prm["recon"] = 1
+    return prm
+
+
+BCS = [[P, P, P, P], [T, T, T, T], [R, R, R, R], [R, T, R, T], [T, R, P, P]]
+SHAPES = [(8, 8), (11, 13), (17, 33), (70, 40)]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: f"{s[0]}x{s[1]}")
+@pytest.mark.parametrize("bc", BCS, ids=lambda b: "".join("PTR"[k] for k in b))
+@pytest.mark.parametrize("geometry", [0, 1], ids=["cart", "cyl"])
+def test_char_small_grids_bitwise(torch, hydro, oracle_mod, shape, bc, geometry):
+    if geometry == 1 and bc[0] == P:
+        pytest.skip("periodic axis in cylindrical geometry")
+    ny, nx = shape
+    xlo = 0.0 if geometry == 1 else -0.3
+    prm = _char(inputs.make_params(nx, ny, xlo, xlo + 1.0, 0.0, 0.8, bc, 1.4, cfl=0.5,
+                                   geometry=geometry, gx=0.05, gy=-0.1))
+    U0 = _random_state(ny, nx, seed=nx * 100 + ny + 1)
+    o = oracle_mod.Oracle(prm)
+    s = hydro.Solver(prm)
+    try:
+        U = _dev(torch, U0)
+        want = U0.copy()
+        for k in range(3):
+            dt = o.cfl(want)
+            assert s.cfl(U) == dt
+            want, al = o.step(want, dt)
+            got_al = s.step(U, dt, return_alpha=True)
+            assert np.array_equal(got_al, al)
+            _same(U.cpu().numpy(), want, f"step {k}")
+    finally:
+        s.close()
+
+
+def test_char_rhs_bitwise(torch, hydro, oracle_mod):
+    prm = _char(inputs.make_params(33, 17, 0.0, 1.0, 0.0, 1.0, [R, T, P, P], 5.0 / 3.0, geometry=1))
+    U0 = _random_state(17, 33, seed=7, gamma=5.0 / 3.0)
+    s = hydro.Solver(prm)
+    try:
+        L = s.rhs(_dev(torch, U0), 2.5, 3.0)
+    finally:
+        s.close()
+    _same(L.cpu().numpy(), oracle_mod.Oracle(prm).rhs(U0, 2.5, 3.0), "L(U)")
+
+
+def test_char_sod_full_run_bitwise(torch, hydro, oracle_mod):
+    prm, U0 = inputs.sod(400)
+    prm = _char(prm)
+    want, t, dts, _ = oracle_mod.Oracle(prm).run(U0, 100000, t_end=0.2)
+    s = hydro.Solver(prm)
+    try:
+        U = _dev(torch, U0)
+        k, tg, _, _ = s.run(U, 100000, t_end=0.2)
+        assert k == len(dts) and tg == t == 0.2
+        _same(U.cpu().numpy(), want, "Sod to t = 0.2")
+    finally:
+        s.close()
+
+
+def test_char_kh_512_bitwise(torch, hydro, oracle_mod):
+    prm, U0 = inputs.kelvin_helmholtz(512, seed=2)
+    prm = _char(prm)
+    want, _, dts, _ = oracle_mod.Oracle(prm).run(U0, 3)
+    s = hydro.Solver(prm)
+    try:
+        U = _dev(torch, U0)
+        s.run(U, 3)
+        _same(U.cpu().numpy(), want, "shear layer 512^2, 3 steps")
+    finally:
+        s.close()
+
+
+def test_char_refusals(torch, hydro):
+    prm = _char(inputs.make_params(16, 16, 0.0, 1.0, 0.0, 1.0, [P] * 4, 1.4))
+    with pytest.raises(hydro.HydroError):
+        hydro.Solver(prm, precision=hydro.FP32_BULK)
+    bad = dict(prm)
+    bad["recon"] = 2
+    with pytest.raises(hydro.HydroError):
+        hydro.Solver(bad)
+    s = hydro.Solver(prm)
+    try:
+        U = _dev(torch, _random_state(16, 16, 3))
+        with pytest.raises(hydro.HydroError):
+            s.step_vjp(U, 1e-3, np.ones((3, 2)), U.clone())
+    finally:
+        s.close()

@@ -1,0 +1,208 @@
+"""GPU parity of the level-set kernels (Sect. 2.3) against the FP64 oracle,
+through the C ABI.
+
+Bit for bit: the advected corner field after several SSP-RK3 steps (every
+boundary combination, grids smaller than one tile and ragged ones, with and
+without a flame speed, periodic inputs whose image corners disagree), the
+corner velocity, the set of front points and the nearest distances.  The
+re-distanced field goes through tanh, whose last bits belong to the math
+library: it is compared within 4e-15 (|S| + d), a few units in the last place
+of the blend's two terms.  Full size: the flame-front workload on 1025^2
+corners (two steps bit for bit, distances at sampled corners).
+"""
+import numpy as np
+import pytest
+
+from paper_1507_08549_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+P, T, R = inputs.PERIODIC, inputs.TRANSMISSIVE, inputs.REFLECTING
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available(), "GPU tests need a GPU"
+    return _t
+
+
+@pytest.fixture(scope="module")
+def hydro():
+    from paper_1507_08549_amd import hydro as _h
+    _h.load()
+    return _h
+
+
+def _dev(torch, a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _same(got, want, what):
+    got = np.asarray(got)
+    if not np.array_equal(got, want):
+        d = np.abs(got - want)
+        k = np.unravel_index(np.argmax(d), d.shape)
+        raise AssertionError(f"{what}: not bitwise equal; max |diff| {d.max():.3e} at {k}")
+
+
+def _field(prm, seed):
+    x, y = inputs.corners(prm)
+    X, Y = np.meshgrid(x, y)
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(0.3, 0.7, 2)
+    S = 0.25 - np.sqrt((X - c[0]) ** 2 + (Y - c[1]) ** 2) + 0.05 * np.sin(7 * X) * np.cos(5 * Y)
+    vel = np.stack([np.sin(np.pi * X) * np.cos(2 * Y) + 0.2, np.cos(3 * X) * Y - 0.1])
+    vel = vel * (1.0 + 0.01 * rng.uniform(-1, 1, vel.shape))
+    return np.ascontiguousarray(S), np.ascontiguousarray(vel)
+
+
+BCS = [(T, T, T, T), (P, P, P, P), (R, T, R, T), (P, P, R, R), (T, R, P, P)]
+SHAPES = [(3, 3), (31, 7), (64, 64), (100, 37), (33, 70)]
+
+
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("shape", SHAPES)
+def test_ls_step_bitwise(torch, hydro, oracle_mod, bc, shape):
+    nx, ny = shape
+    prm = inputs.make_params(nx, ny, 0.0, 1.0, 0.0, 0.8, list(bc), 1.4)
+    S, vel = _field(prm, nx * 100 + ny)
+    ls = oracle_mod.LevelSet(prm)
+    s = hydro.Solver(prm)
+    try:
+        Sd, vd = _dev(torch, S), _dev(torch, vel)
+        want = S
+        for k in range(3):
+            s_f = 0.0 if k == 0 else 0.15
+            s.ls_step(Sd, vd, s_f, 0.004)
+            want = ls.step(want, vel, s_f, 0.004)
+        _same(Sd.cpu().numpy(), want, f"S bc={bc} shape={shape}")
+    finally:
+        s.close()
+
+
+@pytest.mark.parametrize("bc", BCS)
+def test_ls_velocity_bitwise(torch, hydro, oracle_mod, bc):
+    prm = inputs.make_params(37, 21, 0.0, 1.0, 0.0, 1.0, list(bc), 1.4)
+    rng = np.random.default_rng(7)
+    rho = 1.0 + rng.uniform(0, 1, (21, 37))
+    U = inputs.state_from_primitive(rho, rng.uniform(-1, 1, rho.shape), rng.uniform(-1, 1, rho.shape),
+                                    np.ones_like(rho), 1.4)
+    s = hydro.Solver(prm)
+    try:
+        got = s.ls_velocity(_dev(torch, U)).cpu().numpy()
+    finally:
+        s.close()
+    _same(got, oracle_mod.LevelSet(prm).corner_velocity(U), f"velocity bc={bc}")
+
+
+def _sorted_points(p):
+    p = np.asarray(p)
+    return p[np.lexsort((p[:, 1], p[:, 0]))]
+
+
+@pytest.mark.parametrize("shape", [(3, 3), (64, 64), (129, 47)])
+def test_ls_front_and_distance_bitwise(torch, hydro, oracle_mod, shape):
+    nx, ny = shape
+    prm = inputs.make_params(nx, ny, 0.0, 1.0, 0.0, 1.0, [T, T, T, T], 1.4)
+    S, _ = _field(prm, 3 + nx)
+    S[S.shape[0] // 2, 1] = 0.0          # a corner exactly on the front
+    ls = oracle_mod.LevelSet(prm)
+    s = hydro.Solver(prm)
+    try:
+        Sd = _dev(torch, S)
+        pts = s.ls_front(Sd).cpu().numpy()
+        want_pts = ls.front(S)
+        assert len(pts) == len(want_pts) > 0
+        _same(_sorted_points(pts), _sorted_points(want_pts), "front points")
+        dist = torch.zeros_like(Sd)
+        n = s.ls_redistance(Sd, dist)
+        got_S, got_d = Sd.cpu().numpy(), dist.cpu().numpy()
+    finally:
+        s.close()
+    want_S, want_d, wn = ls.redistance(S)
+    assert n == wn
+    _same(got_d, want_d, "distance")
+    tol = 4e-15 * (np.abs(S) + want_d)
+    err = np.abs(got_S - want_S)
+    assert np.all(err <= tol), (err / np.maximum(tol, 1e-300)).max()
+
+
+def test_ls_redistance_without_front(torch, hydro):
+    prm = inputs.make_params(20, 20, 0.0, 1.0, 0.0, 1.0, [T, T, T, T], 1.4)
+    S = 1.0 + np.random.default_rng(1).uniform(0, 1, (21, 21))
+    s = hydro.Solver(prm)
+    try:
+        Sd = _dev(torch, S)
+        dist = torch.full_like(Sd, -1.0)
+        assert s.ls_redistance(Sd, dist) == 0
+        _same(Sd.cpu().numpy(), S, "S")
+        assert bool((dist == -1.0).all())
+    finally:
+        s.close()
+
+
+def test_ls_periodic_images_from_inconsistent_input(torch, hydro, oracle_mod):
+    prm = inputs.make_params(24, 16, 0.0, 1.0, 0.0, 1.0, [P, P, P, P], 1.4)
+    S, vel = _field(prm, 5)
+    S[:, -1] += 0.01                     # the image column disagrees with column 0
+    S[-1, :] -= 0.02
+    s = hydro.Solver(prm)
+    try:
+        Sd = _dev(torch, S)
+        s.ls_step(Sd, _dev(torch, vel), 0.1, 0.01)
+        got = Sd.cpu().numpy()
+    finally:
+        s.close()
+    want = oracle_mod.LevelSet(prm).step(S, vel, 0.1, 0.01)
+    _same(got, want, "S")
+    assert np.array_equal(got[:, -1], got[:, 0]) and np.array_equal(got[-1], got[0])
+
+
+def test_ls_rejects_bad_arguments(torch, hydro):
+    prm1 = inputs.make_params(16, 1, 0.0, 1.0, 0.0, 1.0, [T, T, T, T], 1.4)
+    s = hydro.Solver(prm1)
+    try:
+        S = torch.zeros((2, 17), dtype=torch.float64, device="cuda")
+        vel = torch.zeros((2, 2, 17), dtype=torch.float64, device="cuda")
+        with pytest.raises(hydro.HydroError):
+            s.ls_step(S, vel, 0.0, 0.1)
+    finally:
+        s.close()
+    prm = inputs.make_params(16, 16, 0.0, 1.0, 0.0, 1.0, [T, T, T, T], 1.4)
+    s = hydro.Solver(prm)
+    try:
+        S = torch.zeros((17, 17), dtype=torch.float64, device="cuda")
+        vel = torch.zeros((2, 17, 17), dtype=torch.float64, device="cuda")
+        with pytest.raises(hydro.HydroError):
+            s.ls_step(S, vel, -1.0, 0.1)
+        with pytest.raises(ValueError):
+            s.ls_step(S[:16], vel, 0.0, 0.1)
+    finally:
+        s.close()
+
+
+def test_ls_flame_front_full_size(torch, hydro, oracle_mod):
+    """The flame-front workload at 1024^2 cells (1025^2 corners): two steps bit
+    for bit, then the front and the distances at 4096 sampled corners."""
+    prm, S, vel, s_f = inputs.flame_front(1024)
+    ls = oracle_mod.LevelSet(prm)
+    s = hydro.Solver(prm)
+    try:
+        Sd, vd = _dev(torch, S), _dev(torch, vel)
+        dt = 0.5 / 1024 / (np.abs(vel).max() + s_f)
+        want = S
+        for _ in range(2):
+            s.ls_step(Sd, vd, s_f, dt)
+            want = ls.step(want, vel, s_f, dt)
+        _same(Sd.cpu().numpy(), want, "S after two steps")
+        pts = s.ls_front(Sd).cpu().numpy()
+        _same(_sorted_points(pts), _sorted_points(ls.front(want)), "front points")
+        dist = torch.zeros_like(Sd)
+        s.ls_redistance(Sd, dist)
+        rng = np.random.default_rng(11)
+        js, is_ = rng.integers(0, 1025, 4096), rng.integers(0, 1025, 4096)
+        got = dist.cpu().numpy()[js, is_]
+        _same(got, ls.distance_at(want, js, is_), "sampled distances")
+    finally:
+        s.close()

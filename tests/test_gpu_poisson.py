@@ -1,0 +1,204 @@
+"""GPU parity of the potential solver (Sect. 2.1: Poisson equation in (r, z),
+over-relaxed red-black Gauss-Seidel, reflecting axis and plane, Roche outer
+values, stop on the relative change) and of the acceleration -grad Phi, against
+the FP64 oracle through the C ABI.
+
+FP64 bit for bit: the potential after every iteration, the iteration at which
+the solve stops and the last relative change.  Sizes: ragged grids smaller and
+larger than one workgroup (odd and even nr, nr != nz), then the polytrope
+density at its full size (1024^2) for a bounded number of iterations and at
+256^2 to convergence; the solve feeding the hydro step a live field.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1507_08549_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+R, T = inputs.REFLECTING, inputs.TRANSMISSIVE
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available(), "GPU tests need a GPU"
+    return _t
+
+
+@pytest.fixture(scope="module")
+def hydro():
+    from paper_1507_08549_amd import hydro as _h
+    _h.load()
+    return _h
+
+
+def _dev(torch, a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _quarter_params(nr, nz, rmax, zmax):
+    return inputs.make_params(nr, nz, 0.0, rmax, 0.0, zmax, [R, T, R, T], 4.0 / 3.0,
+                              geometry=inputs.CYLINDRICAL)
+
+
+def _blob(nr, nz, rmax, zmax, seed):
+    """A smooth off-centre density with seeded noise and an empty outer region."""
+    r = (np.arange(nr) + 0.5) * rmax / nr
+    z = (np.arange(nz) + 0.5) * zmax / nz
+    Rr, Zz = np.meshgrid(r, z)
+    d2 = (Rr / (0.45 * rmax)) ** 2 + ((Zz - 0.1 * zmax) / (0.5 * zmax)) ** 2
+    rho = np.where(d2 < 1.0, (1.0 - d2) ** 2, 0.0)
+    rng = np.random.default_rng(seed)
+    return rho * (1.0 + 1e-2 * rng.uniform(-1, 1, rho.shape))
+
+
+def _mass(rho, rmax, zmax):
+    nz, nr = rho.shape
+    dr, dz = rmax / nr, zmax / nz
+    r = (np.arange(nr) + 0.5) * dr
+    return 2.0 * float((2.0 * math.pi * r[None, :] * rho * dr * dz).sum())
+
+
+def _same(got, want, what):
+    if not np.array_equal(got, want):
+        d = np.abs(got - want)
+        k = np.unravel_index(np.argmax(d), d.shape)
+        raise AssertionError(f"{what}: not bitwise equal; max |diff| {d.max():.3e} at {k}")
+
+
+def _solve_both(torch, hydro, oracle_mod, rho, rmax, zmax, omega, tol, max_iter, phi0=None, G=1.0):
+    nz, nr = rho.shape
+    M = _mass(rho, rmax, zmax)
+    s = hydro.Solver(_quarter_params(nr, nz, rmax, zmax))
+    try:
+        phi = _dev(torch, np.zeros_like(rho) if phi0 is None else phi0)
+        it, ch = s.poisson(_dev(torch, rho), phi, G, M, omega=omega, tol=tol, max_iter=max_iter)
+        got = phi.cpu().numpy()
+        g = s.gravity_from_potential(phi, G, M).cpu().numpy()
+    finally:
+        s.close()
+    want, wit, wch = oracle_mod.poisson(rho, rmax, zmax, G, M, phi0=phi0, omega=omega, tol=tol,
+                                        max_iter=max_iter)
+    return (got, it, ch, g), (want, wit, wch, M)
+
+
+@pytest.mark.parametrize("nr,nz", [(7, 5), (33, 29), (64, 64), (50, 17), (129, 200)])
+def test_poisson_bitwise_to_convergence(torch, hydro, oracle_mod, nr, nz):
+    rho = _blob(nr, nz, 1.0, 1.3, seed=nr * 1000 + nz)
+    omega = 2.0 / (1.0 + math.sin(math.pi / max(nr, nz)))
+    (got, it, ch, g), (want, wit, wch, M) = _solve_both(torch, hydro, oracle_mod, rho, 1.0, 1.3,
+                                                        omega, 1e-10, 20000)
+    print(f"nr={nr} nz={nz} iterations {it} (oracle {wit}) change {ch:.3e}")
+    assert wch < 1e-10 and wit < 20000
+    assert it == wit and ch == wch
+    _same(got, want, "phi")
+    _same(g, oracle_mod.gravity_from_potential(want, 1.0, 1.3, 1.0, M), "g")
+
+
+@pytest.mark.parametrize("max_iter", [1, 2, 7, 8, 9, 300])
+def test_poisson_stops_at_max_iter(torch, hydro, oracle_mod, max_iter):
+    """Batches of 8, 16, ... iterations: every batch edge and a partial batch."""
+    rho = _blob(40, 40, 1.0, 1.0, seed=11)
+    (got, it, ch, _), (want, wit, wch, _) = _solve_both(torch, hydro, oracle_mod, rho, 1.0, 1.0,
+                                                        1.5, 1e-14, max_iter)
+    assert wit == max_iter and it == max_iter and ch == wch
+    _same(got, want, "phi")
+
+
+def test_poisson_converges_inside_a_batch(torch, hydro, oracle_mod):
+    """A warm start converges in a few iterations: stop mid-batch, not at its end."""
+    rho = _blob(48, 40, 1.0, 1.0, seed=12)
+    start, _, _ = oracle_mod.poisson(rho, 1.0, 1.0, 1.0, _mass(rho, 1.0, 1.0), omega=1.8, tol=1e-6)
+    (got, it, ch, _), (want, wit, wch, _) = _solve_both(torch, hydro, oracle_mod, rho, 1.0, 1.0,
+                                                        1.8, 1e-7, 10000, phi0=start)
+    print(f"warm start: {wit} iterations")
+    assert 1 < wit < 300
+    assert it == wit and ch == wch
+    _same(got, want, "phi")
+
+
+def test_poisson_polytrope_full_size_bounded(torch, hydro, oracle_mod):
+    """The n = 3 polytrope density at 1024^2: 40 iterations from the Roche guess."""
+    prm, U, _ = inputs.polytrope(1024)
+    rho = U[0]
+    L = prm["xhi"]
+    M = _mass(rho, L, L)
+    r = (np.arange(1024) + 0.5) * L / 1024
+    Rr, Zz = np.meshgrid(r, r)
+    phi0 = -M / np.sqrt(Rr * Rr + Zz * Zz + (0.3 * L) ** 2)
+    omega = 2.0 / (1.0 + math.sin(math.pi / 1024))
+    (got, it, ch, g), (want, wit, wch, _) = _solve_both(torch, hydro, oracle_mod, rho, L, L,
+                                                        omega, 1e-8, 40, phi0=phi0)
+    assert it == wit == 40 and ch == wch
+    _same(got, want, "phi")
+    _same(g, oracle_mod.gravity_from_potential(want, L, L, 1.0, M), "g")
+
+
+def test_poisson_polytrope_converged(torch, hydro, oracle_mod):
+    """The polytrope density at 256^2 solved to the paper's tolerance 1e-8."""
+    prm, U, _ = inputs.polytrope(256)
+    L = prm["xhi"]
+    omega = 2.0 / (1.0 + math.sin(math.pi / 256))
+    (got, it, ch, _), (want, wit, wch, _) = _solve_both(torch, hydro, oracle_mod, U[0], L, L,
+                                                        omega, 1e-8, 50000)
+    print(f"polytrope 256^2: {it} iterations (oracle {wit})")
+    assert it == wit and wch < 1e-8 and ch == wch
+    _same(got, want, "phi")
+
+
+def test_live_gravity_step(torch, hydro, oracle_mod):
+    """Solve, differentiate into the solver's own gravity field, step; the oracle
+    does the same with its potential and field."""
+    n = 96
+    prm, U, _ = inputs.polytrope(n)
+    L = prm["xhi"]
+    M = _mass(U[0], L, L)
+    omega = 2.0 / (1.0 + math.sin(math.pi / n))
+    g_dev = torch.zeros((2, n, n), dtype=torch.float64, device="cuda")
+    s = hydro.Solver(prm, gravity=g_dev)
+    try:
+        Ud = _dev(torch, U)
+        phi = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+        phi_o = np.zeros((n, n))
+        Uo = U.copy()
+        for _ in range(3):
+            s.poisson(Ud[0], phi, 1.0, M, omega=omega, tol=1e-8)
+            s.gravity_from_potential(phi, 1.0, M, out=s.gravity)
+            dt = s.cfl(Ud)
+            s.step(Ud, dt)
+            phi_o, _, _ = oracle_mod.poisson(Uo[0], L, L, 1.0, M, phi0=phi_o, omega=omega, tol=1e-8)
+            go = oracle_mod.gravity_from_potential(phi_o, L, L, 1.0, M)
+            orc = oracle_mod.Oracle(prm, gravity=go)
+            dto = orc.cfl(Uo)
+            assert dt == dto
+            Uo, _ = orc.step(Uo, dto)
+        _same(phi.cpu().numpy(), phi_o, "phi")
+        _same(Ud.cpu().numpy(), Uo, "U")
+    finally:
+        s.close()
+
+
+def test_poisson_rejects_other_geometries(torch, hydro):
+    rho = torch.zeros((16, 16), dtype=torch.float64, device="cuda")
+    phi = torch.zeros_like(rho)
+    cart = inputs.make_params(16, 16, 0.0, 1.0, 0.0, 1.0, [R, T, R, T], 1.4)
+    off = inputs.make_params(16, 16, 0.5, 1.0, 0.0, 1.0, [T, T, R, T], 1.4, geometry=inputs.CYLINDRICAL)
+    for prm in (cart, off):
+        s = hydro.Solver(prm)
+        try:
+            with pytest.raises(hydro.HydroError):
+                s.poisson(rho, phi, 1.0, 1.0)
+        finally:
+            s.close()
+    s = hydro.Solver(_quarter_params(16, 16, 1.0, 1.0))
+    try:
+        for kw in ({"omega": 2.0}, {"omega": 0.0}, {"max_iter": 0}):
+            with pytest.raises(hydro.HydroError):
+                s.poisson(rho, phi, 1.0, 1.0, **kw)
+        with pytest.raises(ValueError):
+            s.poisson(rho[:8], phi, 1.0, 1.0)
+    finally:
+        s.close()

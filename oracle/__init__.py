@@ -90,6 +90,8 @@ def _load():
         pp = ctypes.POINTER(_Params)
         lib.orc_weno5.restype = ctypes.c_double
         lib.orc_weno5.argtypes = [ctypes.c_double] * 6
+        lib.orc_weno5_face.restype = ctypes.c_double
+        lib.orc_weno5_face.argtypes = [ctypes.c_double] * 11
         lib.orc_alpha.argtypes = [pp, dp, dp]
         lib.orc_cfl.argtypes = [pp, dp, dp]
         lib.orc_rhs.argtypes = [pp, dp, dp, ctypes.c_double, ctypes.c_double, dp]
@@ -159,6 +161,13 @@ def weno5(v, eps=1e-6):
     """Scalar WENO5-JS reconstruction at the right face of v[2]."""
     v = [float(x) for x in v]
     return _load().orc_weno5(*v, float(eps))
+
+
+def weno5_face(p, m, eps=1e-6):
+    """Face value: left-biased reconstruction of p[0..4] plus right-biased of
+    m[0..4] (m in upwind order, m[0] farthest), over a common denominator."""
+    v = [float(x) for x in p] + [float(x) for x in m]
+    return _load().orc_weno5_face(*v, float(eps))
 
 
 class Oracle:

@@ -26,7 +26,9 @@
  * Readings of the paper (the paper prints no WENO formula and no rounding
  * rules; these choices are ours and are listed in the design notes):
  *  - point values at cell centres (finite-difference form, Sect. 2.1);
- *  - WENO-JS with eps = p->eps (1e-6 default) and exponent 2;
+ *  - WENO-JS with eps = p->eps (1e-6 default, at least 1e-30) and exponent 2;
+ *    the face value sums the two reconstructions over a common denominator
+ *    (orc_weno5_face);
  *  - "global" LF: alpha_x = max over interior cells of |u|+c, alpha_y =
  *    max of |v|+c, recomputed from every stage's input, same for all four
  *    components (Sect. 2.1);
@@ -77,7 +79,7 @@ static int check_params(const orc_params *p) {
   if (!p) return ORC_E_INVALID;
   if (p->nx < 3 || p->ny < 1 || (p->ny > 1 && p->ny < 3)) return ORC_E_INVALID;
   if (!(p->xhi > p->xlo) || !(p->yhi > p->ylo)) return ORC_E_INVALID;
-  if (!(p->gamma > 1.0) || !(p->eps > 0.0)) return ORC_E_INVALID;
+  if (!(p->gamma > 1.0) || !(p->eps >= 1e-30)) return ORC_E_INVALID;
   for (int k = 0; k < 4; ++k)
     if (p->bc[k] < 0 || p->bc[k] > 2) return ORC_E_INVALID;
   if ((p->bc[0] == ORC_PERIODIC) != (p->bc[1] == ORC_PERIODIC)) return ORC_E_INVALID;
@@ -115,7 +117,8 @@ static prim_t cons_to_prim(double r, double mx, double my, double E, double gamm
  * Written here with p_k = 6 q_k and a_k scaled by 10 s0 s1 s2
  * (s_k = (eps + beta_k)^2):  w0 = s1 s2, w1 = 6 s0 s2, w2 = 3 s0 s1,
  * W = (w0 p0 + w1 p1 + w2 p2) / (6 (w0 + w1 + w2)).  Same value, one division. */
-double orc_weno5(double v0, double v1, double v2, double v3, double v4, double eps) {
+static void weno5_nd(double v0, double v1, double v2, double v3, double v4, double eps, double *num_out,
+                     double *den_out) {
   const double c1312 = 13.0 / 12.0;
   double d, e;
   d = fma(-2.0, v1, v0) + v2;           /* v0 - 2 v1 + v2 */
@@ -138,9 +141,29 @@ double orc_weno5(double v0, double v1, double v2, double v3, double v4, double e
   double w0 = s1 * s2;
   double w1 = 6.0 * (s0 * s2);
   double w2 = 3.0 * (s0 * s1);
-  double num = fma(w2, p2, fma(w1, p1, w0 * p0));
-  double den = 6.0 * ((w0 + w1) + w2);
+  *num_out = fma(w2, p2, fma(w1, p1, w0 * p0));
+  *den_out = 6.0 * ((w0 + w1) + w2);
+}
+
+double orc_weno5(double v0, double v1, double v2, double v3, double v4, double eps) {
+  double num, den;
+  weno5_nd(v0, v1, v2, v3, v4, eps, &num, &den);
   return num / den;
+}
+
+/* Face value of the split flux: the left-biased reconstruction of the f+
+ * stencil p0..p4 plus the right-biased one of the f- stencil m0..m4 (given in
+ * upwind order, m0 the farthest point), over one common denominator:
+ * (n+ d- + n- d+) / (d+ d-).  Two products summed, so the value does not
+ * depend on which side is called "+" (mirror symmetry stays exact); one
+ * division per face instead of two.  d+ d- >= (6 eps^4)^2 stays a normal
+ * double for eps >= 1e-30. */
+double orc_weno5_face(double p0, double p1, double p2, double p3, double p4, double m0, double m1,
+                      double m2, double m3, double m4, double eps) {
+  double np, dp, nm, dm;
+  weno5_nd(p0, p1, p2, p3, p4, eps, &np, &dp);
+  weno5_nd(m0, m1, m2, m3, m4, eps, &nm, &dm);
+  return (np * dm + nm * dp) / (dp * dm);
 }
 
 /* ---------------------------------------------------------- ghost cells */
@@ -347,11 +370,9 @@ static int char_face(const double *fp, const double *fm, int i, const double Ul[
   double gh[4];
   for (int m = 0; m < 4; ++m) {
     const double *l = &L[4 * m];
-    const double wp = orc_weno5(dot4(l, gp[0]), dot4(l, gp[1]), dot4(l, gp[2]), dot4(l, gp[3]),
-                                dot4(l, gp[4]), eps);
-    const double wm = orc_weno5(dot4(l, gm[5]), dot4(l, gm[4]), dot4(l, gm[3]), dot4(l, gm[2]),
-                                dot4(l, gm[1]), eps);
-    gh[m] = wp + wm;
+    gh[m] = orc_weno5_face(dot4(l, gp[0]), dot4(l, gp[1]), dot4(l, gp[2]), dot4(l, gp[3]), dot4(l, gp[4]),
+                           dot4(l, gm[5]), dot4(l, gm[4]), dot4(l, gm[3]), dot4(l, gm[2]), dot4(l, gm[1]),
+                           eps);
   }
   double rot[4];
   for (int c = 0; c < 4; ++c) rot[c] = dot4(&R[4 * c], gh);
@@ -415,11 +436,10 @@ int orc_rhs(const orc_params *p, const double *gravity, const double *V,
         continue;
       }
       for (int c = 0; c < 4; ++c) {
-        double wp = orc_weno5(fp[4 * (i - 2) + c], fp[4 * (i - 1) + c], fp[4 * i + c],
-                              fp[4 * (i + 1) + c], fp[4 * (i + 2) + c], eps);
-        double wm = orc_weno5(fm[4 * (i + 3) + c], fm[4 * (i + 2) + c], fm[4 * (i + 1) + c],
-                              fm[4 * i + c], fm[4 * (i - 1) + c], eps);
-        Fh[4 * f + c] = wp + wm;
+        Fh[4 * f + c] = orc_weno5_face(fp[4 * (i - 2) + c], fp[4 * (i - 1) + c], fp[4 * i + c],
+                                       fp[4 * (i + 1) + c], fp[4 * (i + 2) + c],
+                                       fm[4 * (i + 3) + c], fm[4 * (i + 2) + c], fm[4 * (i + 1) + c],
+                                       fm[4 * i + c], fm[4 * (i - 1) + c], eps);
       }
     }
     for (int i = 0; i < nx; ++i)
@@ -448,11 +468,10 @@ int orc_rhs(const orc_params *p, const double *gravity, const double *V,
           continue;
         }
         for (int c = 0; c < 4; ++c) {
-          double wp = orc_weno5(fp[4 * (jj - 2) + c], fp[4 * (jj - 1) + c], fp[4 * jj + c],
-                                fp[4 * (jj + 1) + c], fp[4 * (jj + 2) + c], eps);
-          double wm = orc_weno5(fm[4 * (jj + 3) + c], fm[4 * (jj + 2) + c], fm[4 * (jj + 1) + c],
-                                fm[4 * jj + c], fm[4 * (jj - 1) + c], eps);
-          Fh[4 * f + c] = wp + wm;
+          Fh[4 * f + c] = orc_weno5_face(fp[4 * (jj - 2) + c], fp[4 * (jj - 1) + c], fp[4 * jj + c],
+                                         fp[4 * (jj + 1) + c], fp[4 * (jj + 2) + c],
+                                         fm[4 * (jj + 3) + c], fm[4 * (jj + 2) + c], fm[4 * (jj + 1) + c],
+                                         fm[4 * jj + c], fm[4 * (jj - 1) + c], eps);
         }
       }
       for (int j = 0; j < ny; ++j)

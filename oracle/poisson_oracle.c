@@ -22,6 +22,9 @@
  *    with M the total mass of the (mirror-symmetric) configuration, an input;
  *  - sweeps in red-black order (colour (i + j) mod 2, red first), which makes
  *    the updates of one colour independent of each other;
+ *  - the Gauss-Seidel value is the weighted neighbour sum minus 4 pi G rho,
+ *    times the reciprocal of the diagonal weight (one reciprocal per column
+ *    and row kind rather than one division per update);
  *  - relative change of a cell |Phi_new - Phi_old| / |Phi_new|, taken as 0
  *    when the value does not change (a cell that stays at 0 gives no 0/0); an
  *    iteration (red then black sweep) ends the solve when the largest one is
@@ -71,7 +74,7 @@ static double sweep(const orc_poisson_params *q, const double *rho, double *phi,
       const double pS = j > 0 ? phi[(size_t)(j - 1) * nr + i] : 0.0;
       const double diag = ((aE + aW) + aN) + aS;
       const double num = (((aE * pE + aW * pW) + aN * pN) + aS * pS) - four_pi_g * rho[(size_t)j * nr + i];
-      const double gs = num / diag;
+      const double gs = num * (1.0 / diag);
       const double old = phi[(size_t)j * nr + i];
       const double nw = old + q->omega * (gs - old);
       phi[(size_t)j * nr + i] = nw;

@@ -149,3 +149,24 @@ def test_eno_property_across_a_jump(oracle_mod):
     assert abs(got) < 1e-9
     got = oracle_mod.weno5([1.0, 1.0, 0.0, 0.0, 0.0], 1e-6)
     assert abs(got) < 1e-9
+
+
+def test_face_value_matches_exact_js_sum(oracle_mod, derived):
+    """The face value W(f+ stencil) + W(f- stencil), formed over one common
+    denominator, equals the sum of the two exact Jiang-Shu reconstructions
+    within a few units in the last place of the larger term; swapping the two
+    sides leaves it bit for bit unchanged, and negating both negates it."""
+    rng = np.random.default_rng(13)
+    for trial in range(60):
+        scale = 10.0 ** rng.uniform(-3, 3)
+        p = list(scale * rng.standard_normal(5))
+        m = list(scale * rng.standard_normal(5))
+        if trial % 3 == 0:
+            p = [p[0], p[0], p[0] + 5 * scale, p[3], p[4]]
+        eps = 1e-6 * scale ** 2 if trial % 2 else 1e-6
+        exact = _js_exact(p, eps, derived) + _js_exact(m, eps, derived)
+        got = oracle_mod.weno5_face(p, m, eps)
+        ref = max(abs(float(_js_exact(p, eps, derived))), abs(float(_js_exact(m, eps, derived))), scale)
+        assert abs(got - float(exact)) <= 8e-15 * ref, (p, m, got, exact)
+        assert oracle_mod.weno5_face(m, p, eps) == got
+        assert oracle_mod.weno5_face([-x for x in p], [-x for x in m], eps) == -got

@@ -65,7 +65,9 @@ enum { HYDRO_COMPONENTWISE = 0, HYDRO_CHARACTERISTIC = 1 };
  *              r = 0 axis and z = 0 plane).  Three ghost layers.
  *  gamma       ideal-gas ratio of specific heats (> 1).
  *  cfl         Courant number c_cfl of the CFL step (Sect. 5.3).
- *  weno_eps    epsilon of the WENO weights (1e-6 is the usual choice).
+ *  weno_eps    epsilon of the WENO weights (1e-6 is the usual choice; at least
+ *              1e-30, so that the two reconstructions of a face can share one
+ *              denominator without underflow).
  *  precision   HYDRO_FP64: every operation in FP64.  HYDRO_FP32_BULK: primitive
  *              variables, split fluxes, reconstructions and the divergence in
  *              FP32; stage accumulation, the CFL / LF-speed reductions and the

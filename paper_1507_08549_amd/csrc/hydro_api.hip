@@ -67,7 +67,7 @@ int check_params(const hydro_params* p) {
   if (p->nx < 3 || p->ny < 1 || (p->ny > 1 && p->ny < 3)) return HYDRO_E_INVALID;
   if ((long long)p->nx * (long long)p->ny > (1LL << 31) - 1) return HYDRO_E_INVALID;
   if (!(p->xhi > p->xlo) || !(p->yhi > p->ylo)) return HYDRO_E_INVALID;
-  if (!(p->gamma > 1.0) || !(p->weno_eps > 0.0) || !(p->cfl > 0.0)) return HYDRO_E_INVALID;
+  if (!(p->gamma > 1.0) || !(p->weno_eps >= 1e-30) || !(p->cfl > 0.0)) return HYDRO_E_INVALID;
   if (!std::isfinite(p->gx) || !std::isfinite(p->gy)) return HYDRO_E_INVALID;
   for (int k = 0; k < 4; ++k)
     if (p->bc[k] < 0 || p->bc[k] > 2) return HYDRO_E_INVALID;
@@ -423,41 +423,11 @@ hy::PoissonArgs poisson_args(const hydro_ctx* c, const double* rho, double* phi,
   a.tol = tol;
   a.rho = rho;
   a.phi = phi;
-  a.ctl = c->ctl;
   return a;
 }
 
 bool poisson_geometry_ok(const hydro_ctx* c) {
   return c->g.cyl && c->g.has_y && c->p.xlo == 0.0 && c->p.ylo == 0.0;
-}
-
-// One launch per colour sweep (the plain order, kept as a cross-check of the
-// blocked solver).
-int poisson_sweeps(hydro_ctx* c, hy::PoissonArgs a, int32_t max_iter, int32_t* iters_out,
-                   double* change_out) {
-  HY_CHECK(hy::launch_poisson_init(c->ctl, c->stream));
-  int k = 0, batch = 8;
-  bool done = false;
-  while (k < max_iter && !done) {
-    const int b = batch < max_iter - k ? batch : max_iter - k;
-    for (int it = k; it < k + b; ++it) {
-      a.iter = it;
-      a.colour = 0;
-      HY_CHECK(hy::launch_poisson_sweep(a, c->stream));
-      a.colour = 1;
-      HY_CHECK(hy::launch_poisson_sweep(a, c->stream));
-    }
-    k += b;
-    a.iter = k;
-    HY_CHECK(hy::launch_poisson_check(a, c->stream));
-    HY_CHECK(hipMemcpyAsync(c->h_ctl, c->ctl, hy::kCtlHeader, hipMemcpyDeviceToHost, c->stream));
-    HY_CHECK(hipStreamSynchronize(c->stream));
-    done = c->h_ctl->pdone != 0;
-    batch = batch < 256 ? 2 * batch : 256;
-  }
-  if (iters_out) *iters_out = done ? c->h_ctl->piters : max_iter;
-  if (change_out) *change_out = c->h_ctl->pchange;
-  return HYDRO_OK;
 }
 
 int ensure_poisson(hydro_ctx* c) {
@@ -484,8 +454,8 @@ int ensure_poisson(hydro_ctx* c) {
 int poisson_blocked(hydro_ctx* c, hy::PoissonArgs a, int32_t max_iter, int32_t* iters_out,
                     double* change_out) {
   if (int rc = ensure_poisson(c)) return rc;
-  const bool big = hy::poisson_block_big(a.nr, a.nz);
-  const int K = hy::poisson_block_k(big);
+  const int config = hy::poisson_block_config(a.nr, a.nz);
+  const int K = hy::poisson_block_k(config);
   a.X[0] = a.phi;
   a.X[1] = c->p_scratch;
   a.pc = c->pc;
@@ -498,7 +468,7 @@ int poisson_blocked(hydro_ctx* c, hy::PoissonArgs a, int32_t max_iter, int32_t* 
       a.kcur = K < max_iter - t ? K : max_iter - t;
       a.t0 = t;
       a.final_ = 0;
-      HY_CHECK(hy::launch_poisson_block(a, big, c->stream));
+      HY_CHECK(hy::launch_poisson_block(a, config, c->stream));
       kprev = a.kcur;
       t += a.kcur;
       ++l;
@@ -509,7 +479,7 @@ int poisson_blocked(hydro_ctx* c, hy::PoissonArgs a, int32_t max_iter, int32_t* 
     a.kcur = 0;
     a.t0 = t;
     a.final_ = t >= max_iter;
-    HY_CHECK(hy::launch_poisson_block(a, big, c->stream));
+    HY_CHECK(hy::launch_poisson_block(a, config, c->stream));
     HY_CHECK(hipMemcpyAsync(c->h_pc, c->pc, 32, hipMemcpyDeviceToHost, c->stream));
     HY_CHECK(hipStreamSynchronize(c->stream));
     if (c->h_pc->done_launch != 0x7fffffff) break;

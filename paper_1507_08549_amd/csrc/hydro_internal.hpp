@@ -47,15 +47,12 @@ constexpr int NSUB = 64;
 struct Ctl {
   double dt;       // time step of the current step (device-computed mode)
   double t;        // time reached
-  double pchange;  // potential solver: largest relative change of the last iteration
+  double pad0;
   int active;      // current step is taken (t < t_end)
   int steps;       // steps taken by hydro_run
   int flag;        // sticky: a stage produced rho <= 0 or p <= 0
-  int pdone;       // potential solver: converged
-  int piters;      // potential solver: iterations done when it converged
-  int pad[5];
+  int pad[7];
   unsigned long long slot[3][NSUB][16];
-  unsigned long long pslot[2][NSUB][16];  // potential solver: max relative change per iteration
 };
 constexpr size_t kCtlHeader = 64;  // bytes before slot[][][]: what the host reads back
 static_assert(offsetof(Ctl, slot) == kCtlHeader, "control header layout");
@@ -109,10 +106,6 @@ struct PoissonArgs {
   double four_pi_g, G, mass, omega, tol;
   const double* rho;
   double* phi;
-  Ctl* ctl;
-  int iter;    // 0-based iteration index
-  int colour;  // 0 red, 1 black
-  // blocked solver
   double* X[2];     // potential buffers: the caller's and a scratch one
   PoissonCtl* pc;
   int l;            // launch index (buffer parity, bank)
@@ -122,12 +115,9 @@ struct PoissonArgs {
   int final_;       // no more launches follow: record the outcome
 };
 hipError_t launch_poisson_block_init(PoissonCtl* pc, hipStream_t s);
-hipError_t launch_poisson_block(const PoissonArgs& a, bool big, hipStream_t s);
-int poisson_block_k(bool big);
-bool poisson_block_big(int nr, int nz);
-hipError_t launch_poisson_init(Ctl* ctl, hipStream_t s);
-hipError_t launch_poisson_sweep(const PoissonArgs& a, hipStream_t s);
-hipError_t launch_poisson_check(const PoissonArgs& a, hipStream_t s);
+hipError_t launch_poisson_block(const PoissonArgs& a, int config, hipStream_t s);
+int poisson_block_k(int config);
+int poisson_block_config(int nr, int nz);
 hipError_t launch_gravity(const PoissonArgs& a, double* g, hipStream_t s);
 
 // Level set on the corners ([ny+1][nx+1]).

@@ -17,33 +17,33 @@
 
 namespace hy {
 
-__device__ __forceinline__ double ieee_next_toward(double q, bool up) {
-  long long b = __double_as_longlong(q);
-  b += ((q > 0.0) == up) ? 1 : -1;
-  return __longlong_as_double(b);
+// q and its neighbour one ulp away from or towards zero: away when the sign
+// of dir matches the sign of q (compared on the high words' sign bits).  A
+// neighbour that is not a finite double of the same sign (from 0 or the
+// largest double) only ever loses the comparison below.
+__device__ __forceinline__ double ieee_step(double q, double dir) {
+  const long long bq = __double_as_longlong(q);
+  const int hi = (int)((unsigned long long)bq >> 32) ^ (int)((unsigned long long)__double_as_longlong(dir) >> 32);
+  return __longlong_as_double(bq + (hi < 0 ? -1LL : 1LL));
 }
 
+// No branches: where t = 0 (exact), q = 0, or q is not finite, the residual of
+// the neighbour is never smaller, so q stays.
 __device__ __forceinline__ double cr_div(double a, double b) {
-  double q = a / b;
+  const double q = a / b;
   const double t = __builtin_fma(-q, b, a);
-  if (t != 0.0 && q != 0.0 && __builtin_isfinite(q)) {
-    const bool up = (t > 0.0) == (b > 0.0);  // a/b lies above q
-    const double q2 = ieee_next_toward(q, up);
-    const double t2 = __builtin_fma(-q2, b, a);
-    if (__builtin_fabs(t2) < __builtin_fabs(t)) q = q2;
-  }
-  return q;
+  // the true quotient q + t/b lies on the side of sign(t) sign(b)
+  const double q2 = ieee_step(q, __builtin_copysign(1.0, t) * b);
+  const double t2 = __builtin_fma(-q2, b, a);
+  return __builtin_fabs(t2) < __builtin_fabs(t) ? q2 : q;
 }
 
 __device__ __forceinline__ double cr_sqrt(double x) {
-  double s = __builtin_sqrt(x);
+  const double s = __builtin_sqrt(x);
   const double t = __builtin_fma(-s, s, x);
-  if (t != 0.0 && s > 0.0 && __builtin_isfinite(s)) {
-    const double s2 = ieee_next_toward(s, t > 0.0);
-    const double t2 = __builtin_fma(-s2, s2, x);
-    if (__builtin_fabs(t2) < __builtin_fabs(t)) s = s2;
-  }
-  return s;
+  const double s2 = ieee_step(s, t);
+  const double t2 = __builtin_fma(-s2, s2, x);
+  return __builtin_fabs(t2) < __builtin_fabs(t) ? s2 : s;
 }
 
 }  // namespace hy

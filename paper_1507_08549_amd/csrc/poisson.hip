@@ -7,17 +7,11 @@
 // Cell-centred five-point stencil, r-operator in flux form (face radii i dr and
 // (i+1) dr, so the axis face has zero weight), mirror at z = 0, Roche values at
 // the outer ghost centres.  Red-black order (colour (i + j) mod 2, red first)
-// makes each colour's updates independent: one launch per colour, one work
-// item per cell of the colour.  Every formula has the CPU oracle's evaluation
-// order (FP64, built with -ffp-contract=off, no fma), so the potential and the
-// iteration count agree bit for bit.
-//
-// Convergence without host round trips: each sweep merges its cells' largest
-// relative change |new - old| / |new| into a ring of two slots (64 sub-slots on
-// separate lines, as for the LF speeds); the red sweep of iteration k reads
-// iteration k-1's slot and, when it is below the tolerance, marks the solve
-// done: every later launch of the batch returns at once.  The black sweep of
-// iteration k clears the slot iteration k+1 will fill.
+// makes each colour's updates independent of each other.  The Gauss-Seidel
+// value is the weighted neighbour sum minus 4 pi G rho times the reciprocal
+// of the diagonal weight.  Every formula has the CPU oracle's evaluation order
+// (FP64, built with -ffp-contract=off, correctly rounded divisions and roots),
+// so the potential and the iteration count agree bit for bit.
 #include "stage_kernel.hpp"
 
 namespace hy {
@@ -26,129 +20,6 @@ constexpr int PS_THREADS = 256;
 
 __device__ __forceinline__ double roche(const PoissonArgs& a, double r, double z) {
   return cr_div(-(a.G * a.mass), cr_sqrt(r * r + z * z));
-}
-
-// Largest relative change recorded in pslot[s] (wavefront 0; broadcast).
-__device__ __forceinline__ double read_pslot(const Ctl* ctl, int s, double* sh) {
-  if (threadIdx.x < NSUB) {
-    double m = as_double(ctl->pslot[s][threadIdx.x][0]);
-#pragma unroll
-    for (int off = NSUB / 2; off > 0; off >>= 1) m = __builtin_fmax(m, __shfl_xor(m, off));
-    if (threadIdx.x == 0) *sh = m;
-  }
-  __syncthreads();
-  return *sh;
-}
-
-__global__ void poisson_init_kernel(Ctl* ctl) {
-  const int t = threadIdx.x;
-  if (t < NSUB) {
-    ctl->pslot[0][t][0] = 0ull;
-    ctl->pslot[1][t][0] = 0ull;
-  }
-  if (t == 0) {
-    ctl->pdone = 0;
-    ctl->piters = 0;
-    ctl->pchange = 0.0;
-  }
-}
-
-hipError_t launch_poisson_init(Ctl* ctl, hipStream_t s) {
-  hipLaunchKernelGGL(poisson_init_kernel, dim3(1), dim3(64), 0, s, ctl);
-  return hipGetLastError();
-}
-
-__global__ __launch_bounds__(PS_THREADS) void poisson_sweep_kernel(PoissonArgs a) {
-  __shared__ double sh;
-  __shared__ double red[PS_THREADS / 64];
-  __shared__ int done;
-  Ctl* ctl = a.ctl;
-  const int tid = threadIdx.x;
-  // one read per workgroup, so that every wavefront takes the same branch
-  if (tid == 0) done = ctl->pdone;
-  __syncthreads();
-  if (done) return;
-  if (a.colour == 0 && a.iter > 0) {
-    const double prev = read_pslot(ctl, (a.iter - 1) & 1, &sh);
-    if (prev < a.tol) {  // converged after iteration iter - 1: same decision in every workgroup
-      if (blockIdx.x == 0 && tid == 0) {
-        ctl->pdone = 1;
-        ctl->piters = a.iter;
-        ctl->pchange = prev;
-      }
-      return;
-    }
-  }
-  if (a.colour == 1 && blockIdx.x == 0 && tid < NSUB) ctl->pslot[(a.iter + 1) & 1][tid][0] = 0ull;
-
-  const int half = (a.nr + 1) / 2;
-  const int cell = blockIdx.x * PS_THREADS + tid;
-  double change = 0.0;
-  if (cell < half * a.nz) {
-    const int j = cell / half;
-    const int i = 2 * (cell % half) + ((j + a.colour) & 1);
-    if (i < a.nr) {
-      const int nr = a.nr, nz = a.nz;
-      const double r_i = ((double)i + 0.5) * a.dr;
-      const double z_j = ((double)j + 0.5) * a.dz;
-      const double wi = cr_div(1.0, (double)i + 0.5);
-      const double aE = ((double)(i + 1) * wi) * a.idr2;
-      const double aW = ((double)i * wi) * a.idr2;
-      const double aN = a.idz2;
-      const double aS = j > 0 ? a.idz2 : 0.0;
-      const double* phi = a.phi;
-      const double pE = i + 1 < nr ? phi[(size_t)j * nr + i + 1] : roche(a, r_i + a.dr, z_j);
-      const double pW = i > 0 ? phi[(size_t)j * nr + i - 1] : 0.0;
-      const double pN = j + 1 < nz ? phi[(size_t)(j + 1) * nr + i] : roche(a, r_i, z_j + a.dz);
-      const double pS = j > 0 ? phi[(size_t)(j - 1) * nr + i] : 0.0;
-      const double diag = ((aE + aW) + aN) + aS;
-      const double num = (((aE * pE + aW * pW) + aN * pN) + aS * pS) - a.four_pi_g * a.rho[(size_t)j * nr + i];
-      const double gs = cr_div(num, diag);
-      const double old = phi[(size_t)j * nr + i];
-      const double nw = old + a.omega * (gs - old);
-      a.phi[(size_t)j * nr + i] = nw;
-      change = nw == old ? 0.0 : cr_div(__builtin_fabs(nw - old), __builtin_fabs(nw));
-    }
-  }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) change = __builtin_fmax(change, __shfl_xor(change, off));
-  if ((tid & 63) == 0) red[tid / 64] = change;
-  __syncthreads();
-  if (tid == 0) {
-    for (int k = 1; k < PS_THREADS / 64; ++k) change = __builtin_fmax(change, red[k]);
-    atomicMax(&ctl->pslot[a.iter & 1][blockIdx.x % NSUB][0], as_bits(change));
-  }
-}
-
-hipError_t launch_poisson_sweep(const PoissonArgs& a, hipStream_t s) {
-  const int half = (a.nr + 1) / 2;
-  const int nb = (half * a.nz + PS_THREADS - 1) / PS_THREADS;
-  hipLaunchKernelGGL(poisson_sweep_kernel, dim3(nb), dim3(PS_THREADS), 0, s, a);
-  return hipGetLastError();
-}
-
-// After iterations 0..iter-1: record convergence of iteration iter-1 (if no
-// sweep has done so already) and its change.
-__global__ void poisson_check_kernel(PoissonArgs a) {
-  __shared__ double sh;
-  __shared__ int done;
-  Ctl* ctl = a.ctl;
-  if (threadIdx.x == 0) done = ctl->pdone;
-  __syncthreads();
-  if (done) return;
-  const double prev = read_pslot(ctl, (a.iter - 1) & 1, &sh);
-  if (threadIdx.x == 0) {
-    ctl->pchange = prev;
-    if (prev < a.tol) {
-      ctl->pdone = 1;
-      ctl->piters = a.iter;
-    }
-  }
-}
-
-hipError_t launch_poisson_check(const PoissonArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(poisson_check_kernel, dim3(1), dim3(64), 0, s, a);
-  return hipGetLastError();
 }
 
 // g = -grad Phi at the cell centres (central differences; mirror across the
@@ -177,7 +48,9 @@ hipError_t launch_gravity(const PoissonArgs& a, double* g, hipStream_t s) {
 
 // ---------------------------------------------------------------------------
 // Temporally blocked solver.  A launch advances its workgroup's tile by up to K
-// iterations without leaving LDS: the tile is loaded with a halo of 2K cells,
+// iterations without leaving LDS (each colour stored contiguously, so a
+// half-sweep reads and writes LDS at unit stride; the r-operator weights once
+// per column; Roche values in the ring beyond the outer edges): the tile is loaded with a halo of 2K cells,
 // and the red (black) half-sweep h updates the cells of its colour within
 // 2K - 1 - h cells of the tile, which are exactly those whose neighbours hold
 // correct values after half-sweep h - 1 (each half-sweep consumes one halo
@@ -194,13 +67,19 @@ hipError_t launch_gravity(const PoissonArgs& a, double* g, hipStream_t s) {
 // decision depends only on l-1's bank, so all workgroups of a launch take the
 // same one, and the launch that ends the solve stamps its index; later
 // launches then return at once.
-template <int TX, int TY, int K>
-__global__ __launch_bounds__(PS_THREADS) void poisson_block_kernel(PoissonArgs a) {
+template <int TX, int TY, int K, int NT>
+__global__ __launch_bounds__(NT) void poisson_block_kernel(PoissonArgs a) {
   constexpr int H = 2 * K;
   constexpr int PX = TX + 2 * H, PY = TY + 2 * H;
-  __shared__ double PH[PY][PX];
-  __shared__ double RH[PY][PX];
-  __shared__ double red[PS_THREADS / 64];
+  constexpr int HX = PX / 2;
+  static_assert(PX % 2 == 0 && TX % 2 == 0 && TY % 2 == 0, "colour layout needs even tiles");
+  // potential and density by colour: cell (lx, ly) of the tile has colour
+  // (lx + ly) & 1 (tile origins are even) and sits at [colour][ly][lx / 2]
+  __shared__ double PC[2][PY][HX];
+  __shared__ double RC[2][PY][HX];
+  __shared__ double cAE[PX], cAW[PX];  // r-operator weights of each column
+  __shared__ double cID[2][PX];        // 1 / diagonal weight: row 0 (no south weight), other rows
+  __shared__ double red[NT / 64];
   __shared__ double sm[PKMAX];
   __shared__ int s_mode, s_m;
   PoissonCtl* pc = a.pc;
@@ -261,52 +140,79 @@ __global__ __launch_bounds__(PS_THREADS) void poisson_block_kernel(PoissonArgs a
   const int ntx = (nr + TX - 1) / TX;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int i0 = (tile % ntx) * TX, j0 = (tile / ntx) * TY;
-  for (int k = tid; k < PX * PY; k += PS_THREADS) {
+  // Load.  Beyond the grid, the ring the stencil reaches holds what the
+  // update takes there: the Roche value past the outer edges (the oracle's
+  // formula at the ghost centre), 0 past the axis and the plane (whose
+  // weights are 0).
+  for (int k = tid; k < PX * PY; k += NT) {
     const int ly = k / PX, lx = k % PX;
     const int i = i0 - H + lx, j = j0 - H + ly;
+    const bool iin = i >= 0 && i < nr, jin = j >= 0 && j < nz;
     double p = 0.0, r = 0.0;
-    if (i >= 0 && i < nr && j >= 0 && j < nz) {
+    if (iin && jin) {
       p = in[(size_t)j * nr + i];
       r = a.rho[(size_t)j * nr + i];
+    } else if (i == nr && jin) {
+      p = roche(a, ((double)(nr - 1) + 0.5) * a.dr + a.dr, ((double)j + 0.5) * a.dz);
+    } else if (j == nz && iin) {
+      p = roche(a, ((double)i + 0.5) * a.dr, ((double)(nz - 1) + 0.5) * a.dz + a.dz);
     }
-    PH[ly][lx] = p;
-    RH[ly][lx] = r;
+    const int c = (lx + ly) & 1;
+    PC[c][ly][lx >> 1] = p;
+    RC[c][ly][lx >> 1] = r;
+  }
+  for (int lx = tid; lx < PX; lx += NT) {
+    const int i = i0 - H + lx;
+    double e = 0.0, w = 0.0, d0 = 0.0, d1 = 0.0;
+    if (i >= 0 && i < nr) {
+      const double wi = cr_div(1.0, (double)i + 0.5);
+      e = ((double)(i + 1) * wi) * a.idr2;  // r_{i+1/2} / (r_i dr^2)
+      w = ((double)i * wi) * a.idr2;        // r_{i-1/2} / (r_i dr^2)
+      d0 = cr_div(1.0, ((e + w) + a.idz2) + 0.0);
+      d1 = cr_div(1.0, ((e + w) + a.idz2) + a.idz2);
+    }
+    cAE[lx] = e;
+    cAW[lx] = w;
+    cID[0][lx] = d0;
+    cID[1][lx] = d1;
   }
   __syncthreads();
 
   const int ti1 = min(i0 + TX, nr) - 1, tj1 = min(j0 + TY, nz) - 1;  // owned cells (inclusive)
+  const int ox = i0 - H, oy = j0 - H;  // tile origin of the LDS arrays
+  const int tr = tid / 32, tm = tid % 32;
+  constexpr int MW = (HX + 31) / 32;
   double change = 0.0;
   for (int h = 0; h < 2 * kk; ++h) {
     const int c = h & 1;
     const int g = 2 * kk - 1 - h;
-    const int ia = max(i0 - g, 0), ib = min(ti1 + g, nr - 1);
-    const int ja = max(j0 - g, 0), jb = min(tj1 + g, nz - 1);
-    const int wmax = ((ib - ia) >> 1) + 1;
-    const int ncell = (jb - ja + 1) * wmax;
-    for (int t = tid; t < ncell; t += PS_THREADS) {
-      const int j = ja + t / wmax;
-      const int i = ia + ((c + j + ia) & 1) + 2 * (t % wmax);
-      if (i > ib) continue;
-      const int lx = i - i0 + H, ly = j - j0 + H;
-      const double r_i = ((double)i + 0.5) * a.dr;
-      const double z_j = ((double)j + 0.5) * a.dz;
-      const double wi = cr_div(1.0, (double)i + 0.5);
-      const double aE = ((double)(i + 1) * wi) * a.idr2;
-      const double aW = ((double)i * wi) * a.idr2;
-      const double aN = a.idz2;
+    const int lxa = max(i0 - g, 0) - ox, lxb = min(ti1 + g, nr - 1) - ox;
+    const int lya = max(j0 - g, 0) - oy, lyb = min(tj1 + g, nz - 1) - oy;
+    const double(*Q)[HX] = PC[1 - c];
+    for (int ly = lya + tr; ly <= lyb; ly += NT / 32) {
+      const int o = (c + ly) & 1;  // cells of colour c in this row: lx = 2m + o
+      const int mlo = (lxa - o + 1) >> 1, mhi = (lxb - o) >> 1;
+      const int j = oy + ly;
       const double aS = j > 0 ? a.idz2 : 0.0;
-      const double pE = i + 1 < nr ? PH[ly][lx + 1] : roche(a, r_i + a.dr, z_j);
-      const double pW = i > 0 ? PH[ly][lx - 1] : 0.0;
-      const double pN = j + 1 < nz ? PH[ly + 1][lx] : roche(a, r_i, z_j + a.dz);
-      const double pS = j > 0 ? PH[ly - 1][lx] : 0.0;
-      const double diag = ((aE + aW) + aN) + aS;
-      const double num = (((aE * pE + aW * pW) + aN * pN) + aS * pS) - a.four_pi_g * RH[ly][lx];
-      const double gs = cr_div(num, diag);
-      const double old = PH[ly][lx];
-      const double nw = old + a.omega * (gs - old);
-      PH[ly][lx] = nw;
-      if (i >= i0 && i <= ti1 && j >= j0 && j <= tj1)
-        change = __builtin_fmax(change, nw == old ? 0.0 : cr_div(__builtin_fabs(nw - old), __builtin_fabs(nw)));
+      const double* ID = cID[j > 0 ? 1 : 0];
+      // up to MW cells of the row per work item, independent of each other
+#pragma unroll
+      for (int w = 0; w < MW; ++w) {
+        const int m = mlo + tm + 32 * w;
+        if (m > mhi) continue;
+        const int lx = 2 * m + o;
+        const double aE = cAE[lx], aW = cAW[lx], aN = a.idz2;
+        const double pE = Q[ly][m + o], pW = Q[ly][m + o - 1];
+        const double pN = Q[ly + 1][m], pS = Q[ly - 1][m];
+        const double num = (((aE * pE + aW * pW) + aN * pN) + aS * pS) - a.four_pi_g * RC[c][ly][m];
+        const double gs = num * ID[lx];
+        const double old = PC[c][ly][m];
+        const double nw = old + a.omega * (gs - old);
+        PC[c][ly][m] = nw;
+        const int i = ox + lx;
+        if (i >= i0 && i <= ti1 && j >= j0 && j <= tj1)
+          change = __builtin_fmax(change, nw == old ? 0.0 : cr_div(__builtin_fabs(nw - old), __builtin_fabs(nw)));
+      }
     }
     __syncthreads();
     if (c == 1 && !redo) {
@@ -316,16 +222,19 @@ __global__ __launch_bounds__(PS_THREADS) void poisson_block_kernel(PoissonArgs a
       if ((tid & 63) == 0) red[tid / 64] = change;
       __syncthreads();
       if (tid == 0) {
-        double m = red[0];
-        for (int k = 1; k < PS_THREADS / 64; ++k) m = __builtin_fmax(m, red[k]);
-        atomicMax(&pc->bank[bank][h >> 1][blockIdx.x % NSUB][0], as_bits(m));
+        double mx = red[0];
+        for (int k = 1; k < NT / 64; ++k) mx = __builtin_fmax(mx, red[k]);
+        atomicMax(&pc->bank[bank][h >> 1][blockIdx.x % NSUB][0], as_bits(mx));
       }
       change = 0.0;
     }
   }
-  for (int k = tid; k < TX * TY; k += PS_THREADS) {
+  for (int k = tid; k < TX * TY; k += NT) {
     const int i = i0 + k % TX, j = j0 + k / TX;
-    if (i < nr && j < nz) out[(size_t)j * nr + i] = PH[j - j0 + H][i - i0 + H];
+    if (i < nr && j < nz) {
+      const int lx = i - ox, ly = j - oy;
+      out[(size_t)j * nr + i] = PC[(lx + ly) & 1][ly][lx >> 1];
+    }
   }
 }
 
@@ -343,27 +252,36 @@ __global__ void poisson_block_init_kernel(PoissonCtl* pc) {
 }
 
 namespace {
-constexpr int BTX = 64, BTY = 32, BK = 4;  // large grids: 80 x 48 cells in LDS (61 KB)
-constexpr int STX = 16, STY = 16, SK = 2;  // small grids: 24 x 24 cells in LDS (9 KB)
-static_assert(BK <= PKMAX && SK <= PKMAX, "bank depth");
+constexpr int BTX = 128, BTY = 32, BK = 4, BNT = 1024;  // large grids: 144 x 48 cells in LDS (115 KB)
+constexpr int MTX = 32, MTY = 32, MK = 4, MNT = 256;    // mid-size grids: 48 x 48 cells in LDS (39 KB)
+constexpr int STX = 16, STY = 16, SK = 2, SNT = 256;  // small grids: 24 x 24 cells in LDS (9 KB)
+static_assert(BK <= PKMAX && MK <= PKMAX && SK <= PKMAX, "bank depth");
 int tiles(int nr, int nz, int tx, int ty) { return ((nr + tx - 1) / tx) * ((nz + ty - 1) / ty); }
 }  // namespace
 
-bool poisson_block_big(int nr, int nz) { return tiles(nr, nz, BTX, BTY) >= 256; }
-int poisson_block_k(bool big) { return big ? BK : SK; }
+// The largest tile shape that still gives every compute unit a workgroup.
+int poisson_block_config(int nr, int nz) {
+  if (tiles(nr, nz, BTX, BTY) >= 256) return 2;
+  if (tiles(nr, nz, MTX, MTY) >= 256) return 1;
+  return 0;
+}
+int poisson_block_k(int config) { return config == 2 ? BK : (config == 1 ? MK : SK); }
 
 hipError_t launch_poisson_block_init(PoissonCtl* pc, hipStream_t s) {
   hipLaunchKernelGGL(poisson_block_init_kernel, dim3(1), dim3(64), 0, s, pc);
   return hipGetLastError();
 }
 
-hipError_t launch_poisson_block(const PoissonArgs& a, bool big, hipStream_t s) {
-  if (big)
-    hipLaunchKernelGGL((poisson_block_kernel<BTX, BTY, BK>), dim3(tiles(a.nr, a.nz, BTX, BTY)),
-                       dim3(PS_THREADS), 0, s, a);
+hipError_t launch_poisson_block(const PoissonArgs& a, int config, hipStream_t s) {
+  if (config == 2)
+    hipLaunchKernelGGL((poisson_block_kernel<BTX, BTY, BK, BNT>), dim3(tiles(a.nr, a.nz, BTX, BTY)),
+                       dim3(BNT), 0, s, a);
+  else if (config == 1)
+    hipLaunchKernelGGL((poisson_block_kernel<MTX, MTY, MK, MNT>), dim3(tiles(a.nr, a.nz, MTX, MTY)),
+                       dim3(MNT), 0, s, a);
   else
-    hipLaunchKernelGGL((poisson_block_kernel<STX, STY, SK>), dim3(tiles(a.nr, a.nz, STX, STY)),
-                       dim3(PS_THREADS), 0, s, a);
+    hipLaunchKernelGGL((poisson_block_kernel<STX, STY, SK, SNT>), dim3(tiles(a.nr, a.nz, STX, STY)),
+                       dim3(SNT), 0, s, a);
   return hipGetLastError();
 }
 

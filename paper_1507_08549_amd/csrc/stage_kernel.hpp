@@ -74,10 +74,10 @@ __device__ __forceinline__ Prim<double> prim(double r, double mx, double my, dou
   return w;
 }
 
-// WENO5-JS at the right face of v2, one division (weights over the common
-// denominator 10 s0 s1 s2, s_k = (eps + beta_k)^2).
-__device__ __forceinline__ double weno5(double v0, double v1, double v2, double v3, double v4,
-                                        double eps) {
+// WENO5-JS at the right face of v2 as numerator and denominator (weights over
+// the common denominator 10 s0 s1 s2, s_k = (eps + beta_k)^2): W = num / den.
+__device__ __forceinline__ void weno5_nd(double v0, double v1, double v2, double v3, double v4, double eps,
+                                         double& num, double& den) {
   const double c1312 = 13.0 / 12.0;
   double d = __builtin_fma(-2.0, v1, v0) + v2;
   double e = __builtin_fma(3.0, v2, __builtin_fma(-4.0, v1, v0));
@@ -97,9 +97,28 @@ __device__ __forceinline__ double weno5(double v0, double v1, double v2, double 
   double w0 = s1 * s2;
   double w1 = 6.0 * (s0 * s2);
   double w2 = 3.0 * (s0 * s1);
-  double num = __builtin_fma(w2, p2, __builtin_fma(w1, p1, w0 * p0));
-  double den = 6.0 * ((w0 + w1) + w2);
+  num = __builtin_fma(w2, p2, __builtin_fma(w1, p1, w0 * p0));
+  den = 6.0 * ((w0 + w1) + w2);
+}
+
+__device__ __forceinline__ double weno5(double v0, double v1, double v2, double v3, double v4,
+                                        double eps) {
+  double num, den;
+  weno5_nd(v0, v1, v2, v3, v4, eps, num, den);
   return cr_div(num, den);
+}
+
+// Face value of a split flux: left-biased reconstruction of the f+ stencil
+// p0..p4 plus right-biased reconstruction of the f- stencil m0..m4 (upwind
+// order), over one common denominator, (n+ d- + n- d+) / (d+ d-): one division
+// per face; symmetric in the two sides.
+__device__ __forceinline__ double weno5_face(double p0, double p1, double p2, double p3, double p4,
+                                             double m0, double m1, double m2, double m3, double m4,
+                                             double eps) {
+  double np, dp, nm, dm;
+  weno5_nd(p0, p1, p2, p3, p4, eps, np, dp);
+  weno5_nd(m0, m1, m2, m3, m4, eps, nm, dm);
+  return cr_div(np * dm + nm * dp, dp * dm);
 }
 
 __device__ __forceinline__ double lf_fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
@@ -222,7 +241,7 @@ __device__ __forceinline__ bool char_face(const double* F, const double* Q, int 
         h[k] = dot4(l0, l1, l2, l3, f);
       }
     }
-    gh[m] = weno5(g[0], g[1], g[2], g[3], g[4], eps) + weno5(h[5], h[4], h[3], h[2], h[1], eps);
+    gh[m] = weno5_face(g[0], g[1], g[2], g[3], g[4], h[5], h[4], h[3], h[2], h[1], eps);
   }
   const double r0 = dot4(1.0, 1.0, 0.0, 1.0, gh);
   const double r1 = dot4(un - c, un, 0.0, un + c, gh);
@@ -427,7 +446,10 @@ __global__ __launch_bounds__(TX* TY) void stage_kernel(StageArgs a) {
           const int j = rest % TY, c = rest / TY;
           const R* P = &sF[c][j * TXP + f];
           const R* M = &sF[4 + c][j * TXP + f];
-          fh[kk] = weno5(P[0], P[1], P[2], P[3], P[4], eps) + weno5(M[5], M[4], M[3], M[2], M[1], eps);
+          if constexpr (sizeof(R) == 8)
+            fh[kk] = weno5_face(P[0], P[1], P[2], P[3], P[4], M[5], M[4], M[3], M[2], M[1], eps);
+          else
+            fh[kk] = weno5(P[0], P[1], P[2], P[3], P[4], eps) + weno5(M[5], M[4], M[3], M[2], M[1], eps);
         }
       }
       __syncthreads();
@@ -491,8 +513,12 @@ __global__ __launch_bounds__(TX* TY) void stage_kernel(StageArgs a) {
           const int f = rest % (TY + 1), c = rest / (TY + 1);
           const R* P = &sF[c][f * TX + i];
           const R* M = &sF[4 + c][f * TX + i];
-          fh[kk] = weno5(P[0], P[TX], P[2 * TX], P[3 * TX], P[4 * TX], eps) +
-                   weno5(M[5 * TX], M[4 * TX], M[3 * TX], M[2 * TX], M[TX], eps);
+          if constexpr (sizeof(R) == 8)
+            fh[kk] = weno5_face(P[0], P[TX], P[2 * TX], P[3 * TX], P[4 * TX], M[5 * TX], M[4 * TX],
+                                M[3 * TX], M[2 * TX], M[TX], eps);
+          else
+            fh[kk] = weno5(P[0], P[TX], P[2 * TX], P[3 * TX], P[4 * TX], eps) +
+                     weno5(M[5 * TX], M[4 * TX], M[3 * TX], M[2 * TX], M[TX], eps);
         }
       }
       __syncthreads();

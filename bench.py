@@ -13,7 +13,9 @@ form's rate and its relative L1 density error against the FP64 oracle, the
 roofline of the stage kernel, the oracle's own rate on the host cores, and the
 adjoint workload (sine-mode shear layer, 1024^2, 500 steps, checkpoints every
 50: backward/forward time ratio in FP64 and FP32, central-difference check,
-FP32-vs-FP64 gradient error).
+FP32-vs-FP64 gradient error), and the potential solver on the polytrope
+density (1024^2, red-black over-relaxation to the relative change 1e-8), and
+the level-set flame front (1025^2 corners: advection step and re-distancing).
 """
 from __future__ import annotations
 
@@ -40,6 +42,35 @@ FLOPS_PER_CELL_STAGE = 2 * 41 + 2 * (8 * 66 + 4) + 64
 BYTES_PER_CELL_STEP = 32 * (2 + 3 + 3)
 PEAK_FP64_VALU_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
+# Algorithmic bytes of one red-black iteration per cell: rho once, the
+# potential read twice (as a cell of its colour and as a neighbour of the
+# other) and written once (FP64).
+POISSON_BYTES_PER_CELL_ITER = 8 * 4
+
+
+# HBM traffic of one stage-kernel launch on this workload, from two rocprofv3
+# --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by the factors a 256 MiB device
+# copy gives (x2.0 for FETCH, x1.0 for WRITE); the summary, with the commands,
+# is under profiles/.  It holds for the kernel sources with this digest only:
+# after any change to them the figure is reported as null until re-measured.
+STAGE_TRAFFIC = {
+    "sources": ["paper_1507_08549_amd/csrc/stage_kernel.hpp", "paper_1507_08549_amd/csrc/ieee.hpp",
+                "paper_1507_08549_amd/csrc/stage_fp64.hip", "paper_1507_08549_amd/csrc/hydro_internal.hpp"],
+    "sha256": "4e710615df86899669f2016dc0ad584dcf355a0274315095b874dcf9bbfb3492",
+    "n": 512,
+    "bytes_per_launch": (15.183 + 8.489) * 1e6,
+}
+
+
+def stage_traffic(n):
+    import hashlib
+    h = hashlib.sha256()
+    for f in STAGE_TRAFFIC["sources"]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != STAGE_TRAFFIC["sha256"] or n != STAGE_TRAFFIC["n"]:
+        return None
+    return STAGE_TRAFFIC["bytes_per_launch"]
 
 
 def log(*a):
@@ -112,6 +143,101 @@ def fd_check(torch, inputs, s, a_np, sched, comps, h=1e-7):
     return np.array(out)
 
 
+def poisson_leg(torch, hydro, inputs, n, cpu_iters):
+    """Potential of the n = 3 polytrope's density from a zero start to the
+    relative change 1e-8 with the near-optimal over-relaxation factor."""
+    import math
+    prm, U0, _ = inputs.polytrope(n)
+    L = prm["xhi"]
+    rho_np = np.ascontiguousarray(U0[0])
+    dr = L / n
+    r = (np.arange(n) + 0.5) * dr
+    mass = 2.0 * float((2.0 * math.pi * r[None, :] * rho_np * dr * dr).sum())
+    omega = 2.0 / (1.0 + math.sin(math.pi / n))
+    qprm = inputs.make_params(n, n, 0.0, L, 0.0, L, prm["bc"], prm["gamma"], geometry=inputs.CYLINDRICAL)
+    s = hydro.Solver(qprm)
+    rho = torch.tensor(rho_np, dtype=torch.float64, device="cuda")
+    phi = torch.zeros_like(rho)
+    s.poisson(rho, phi, 1.0, mass, omega=omega, tol=1e-8, max_iter=50)  # warm-up
+    phi.zero_()
+    st = s.stream
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    t0 = time.perf_counter()
+    iters, change = s.poisson(rho, phi, 1.0, mass, omega=omega, tol=1e-8, max_iter=200000)
+    e1.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    t = e0.elapsed_time(e1) / 1e3
+    out = {"workload": f"polytrope_density_{n}x{n}_zero_start_tol1e-8", "omega": omega,
+           "iterations": iters, "last_change": change, "ms": t * 1e3, "wall_ms": wall * 1e3,
+           "cell_iterations_per_s": n * n * iters / t,
+           "us_per_iteration": t * 1e6 / iters,
+           "hbm_gbs_algorithmic": POISSON_BYTES_PER_CELL_ITER * n * n * iters / t / 1e9}
+    out["hbm_frac"] = out["hbm_gbs_algorithmic"] / PEAK_HBM_GBS
+    log(f"poisson: {iters} iterations in {t * 1e3:.1f} ms ({out['us_per_iteration']:.2f} us/iteration, "
+        f"{out['hbm_gbs_algorithmic']:.0f} GB/s algorithmic)")
+    if cpu_iters > 0:
+        import oracle
+        c0 = time.perf_counter()
+        ref, _, _ = oracle.poisson(rho_np, L, L, 1.0, mass, omega=omega, tol=0.0, max_iter=cpu_iters)
+        ct = time.perf_counter() - c0
+        phi.zero_()
+        s.poisson(rho, phi, 1.0, mass, omega=omega, tol=0.0, max_iter=cpu_iters)
+        out["cpu_oracle"] = {"cell_iterations_per_s": n * n * cpu_iters / ct, "cores": 1,
+                             "sample": f"{cpu_iters} iterations, {ct:.1f} s",
+                             "fp64_bitwise_equal": bool(np.array_equal(phi.cpu().numpy(), ref))}
+    s.close()
+    return out
+
+
+def levelset_leg(torch, hydro, inputs, n, steps, cpu):
+    """Level-set flame front on (n+1)^2 corners: `steps` rounds of one SSP-RK3
+    advection step and one re-distancing, each timed with HIP events."""
+    prm, S0, vel_np, s_f = inputs.flame_front(n)
+    s = hydro.Solver(prm)
+    S = torch.tensor(S0, dtype=torch.float64, device="cuda")
+    vel = torch.tensor(vel_np, dtype=torch.float64, device="cuda")
+    dt = 0.5 / n / (float(np.abs(vel_np).max()) + s_f)
+    st = s.stream
+    for _ in range(2):
+        s.ls_step(S, vel, s_f, dt)
+        s.ls_redistance(S)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    t_step = t_red = 0.0
+    npts = 0
+    for _ in range(steps):
+        ev[0].record(st)
+        s.ls_step(S, vel, s_f, dt)
+        ev[1].record(st)
+        npts = s.ls_redistance(S)
+        ev[2].record(st)
+        torch.cuda.synchronize()
+        t_step += ev[0].elapsed_time(ev[1]) / 1e3
+        t_red += ev[1].elapsed_time(ev[2]) / 1e3
+    nc = (n + 1) * (n + 1)
+    out = {"workload": f"flame_front_{n}x{n}_cells_{n + 1}x{n + 1}_corners", "steps": steps,
+           "step_us": t_step * 1e6 / steps, "redistance_us": t_red * 1e6 / steps,
+           "front_points": npts,
+           "corner_updates_per_s": nc * steps / t_step,
+           "distance_pairs_per_s_bruteforce_equiv": float(nc) * npts * steps / t_red}
+    log(f"levelset: step {out['step_us']:.1f} us, redistance {out['redistance_us']:.1f} us "
+        f"({npts} front points)")
+    if cpu:
+        import oracle
+        ls = oracle.LevelSet(prm)
+        c0 = time.perf_counter()
+        ls.step(S0, vel_np, s_f, dt)
+        ct = time.perf_counter() - c0
+        out["cpu_oracle"] = {"corner_updates_per_s": nc / ct, "cores": 1,
+                             "sample": f"one advection step at full size, {ct:.2f} s"}
+    s.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -124,6 +250,11 @@ def main():
     ap.add_argument("--adj-n", type=int, default=1024, help="adjoint workload grid (n x n; 0: skip)")
     ap.add_argument("--adj-steps", type=int, default=500)
     ap.add_argument("--adj-ckpt", type=int, default=50)
+    ap.add_argument("--poisson-n", type=int, default=1024,
+                    help="potential-solver workload grid (n x n; 0: skip)")
+    ap.add_argument("--poisson-cpu-iters", type=int, default=200)
+    ap.add_argument("--ls-n", type=int, default=1024, help="level-set workload cells per side (0: skip)")
+    ap.add_argument("--ls-steps", type=int, default=20)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB three times (a known-size "
                          "kernel for calibrating the profiler's HBM byte counters)")
@@ -216,6 +347,15 @@ def main():
             f"fp32 ratio {adj['ratio_fp32']:.2f}, FD rel err {fd_err:.2e}, "
             f"fp32 grad rel err {adj['grad_rel_err_fp32_vs_fp64']:.2e}")
 
+    pois = None
+    if args.poisson_n > 0:
+        pois = poisson_leg(torch, hydro, inputs, args.poisson_n,
+                           args.poisson_cpu_iters if args.cpu_steps > 0 else 0)
+
+    lset = None
+    if args.ls_n > 0:
+        lset = levelset_leg(torch, hydro, inputs, args.ls_n, args.ls_steps, args.cpu_steps > 0)
+
     out = {
         "metric": "cell-updates/sec per RK3 step FP64 vs FP32 at stated L1 err; adjoint/fwd ratio",
         "value": v64,
@@ -233,12 +373,16 @@ def main():
                    "cfl": 0.5, "bc": "periodic", "seed": 2, "precision": "fp64"},
         "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": PEAK_FP64_VALU_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tf / PEAK_FP64_VALU_TFLOPS,
-                     "traffic": None, "kernel": "stage_kernel<double,16,16>",
+                     "traffic": stage_traffic(n), "traffic_unit": "bytes per launch",
+                     "algorithmic_bytes_per_launch": BYTES_PER_CELL_STEP * ncell / 3,
+                     "kernel": "stage_kernel<double,16,16>",
                      "avg_launch_us": stage_s * 1e6, "hbm_gbs_algorithmic": hbm_gbs,
                      "hbm_frac": hbm_gbs / PEAK_HBM_GBS},
         "cpu_baseline": cpu,
         "fp32_bulk": fp32,
         "adjoint": adj,
+        "poisson": pois,
+        "levelset": lset,
     }
     print(json.dumps(out), flush=True)
 

@@ -6,8 +6,9 @@ the FP64 oracle through the C ABI.
 FP64 bit for bit: the potential after every iteration, the iteration at which
 the solve stops and the last relative change.  Sizes: ragged grids smaller and
 larger than one workgroup (odd and even nr, nr != nz), then the polytrope
-density at its full size (1024^2) for a bounded number of iterations and at
-256^2 to convergence; the solve feeding the hydro step a live field.
+density at its full size (1024^2) and at 512^2 (the three tile shapes) for a
+bounded number of iterations and at 256^2 to convergence; the solve feeding
+the hydro step a live field.
 """
 import math
 
@@ -133,6 +134,22 @@ def test_poisson_polytrope_full_size_bounded(torch, hydro, oracle_mod):
     (got, it, ch, g), (want, wit, wch, _) = _solve_both(torch, hydro, oracle_mod, rho, L, L,
                                                         omega, 1e-8, 40, phi0=phi0)
     assert it == wit == 40 and ch == wch
+    _same(got, want, "phi")
+    _same(g, oracle_mod.gravity_from_potential(want, L, L, 1.0, M), "g")
+
+
+def test_poisson_mid_size_bounded(torch, hydro, oracle_mod):
+    """512^2 runs the mid-size tile shape (32 x 32, 4 iterations per launch)."""
+    prm, U, _ = inputs.polytrope(512)
+    L = prm["xhi"]
+    M = _mass(U[0], L, L)
+    r = (np.arange(512) + 0.5) * L / 512
+    Rr, Zz = np.meshgrid(r, r)
+    phi0 = -M / np.sqrt(Rr * Rr + Zz * Zz + (0.3 * L) ** 2)
+    omega = 2.0 / (1.0 + math.sin(math.pi / 512))
+    (got, it, ch, g), (want, wit, wch, _) = _solve_both(torch, hydro, oracle_mod, U[0], L, L,
+                                                        omega, 1e-8, 37, phi0=phi0)
+    assert it == wit == 37 and ch == wch
     _same(got, want, "phi")
     _same(g, oracle_mod.gravity_from_potential(want, L, L, 1.0, M), "g")
 

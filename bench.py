@@ -11,9 +11,9 @@ the timed region starts.
 Reported (one JSON line): FP64 cell-updates/s (the value), the FP32-bulk
 form's rate and its relative L1 density error against the FP64 oracle, the
 roofline of the stage kernel, the oracle's own rate on the host cores, and the
-adjoint workload (sine-mode shear layer, 1024^2, 500 steps, checkpoints every
-50: backward/forward time ratio in FP64 and FP32, central-difference check,
-FP32-vs-FP64 gradient error), and the potential solver on the polytrope
+adjoint workload (sine-mode shear layer, 1024^2, 500 steps: backward/forward
+time ratio in FP64 and FP32 keeping every state, and with checkpoints every
+50 steps; central-difference check; FP32-vs-FP64 gradient error), and the potential solver on the polytrope
 density (1024^2, red-black over-relaxation to the relative change 1e-8), and
 the level-set flame front (1025^2 corners: advection step and re-distancing).
 """
@@ -94,8 +94,9 @@ def timed_run(torch, solver, U, steps):
 
 def adjoint_leg(torch, hydro, inputs, n, steps, ckpt, precision, a_np, sched=None):
     """Gradient of the final y-kinetic energy of the sine-mode shear layer with
-    respect to its mode amplitudes, by the hand-written adjoint (checkpointed
-    rollout).  Returns (J, grad, forward seconds, backward seconds, schedule)."""
+    respect to its mode amplitudes, by the hand-written adjoint (rollout keeping
+    every state when ckpt is None, else checkpointed every ckpt steps).
+    Returns (solver, J, grad, forward seconds, backward seconds, schedule)."""
     from paper_1507_08549_amd.autograd import rollout
     prm = inputs.kh_sine_params(n)
     s = hydro.Solver(prm, precision=precision)
@@ -114,7 +115,7 @@ def adjoint_leg(torch, hydro, inputs, n, steps, ckpt, precision, a_np, sched=Non
         t2 = time.perf_counter()
         return J.item(), g.cpu().numpy(), t1 - t0, t2 - t1
 
-    once(min(steps, 2 * ckpt))  # warm-up (allocations, code objects)
+    once(min(steps, 2 * (ckpt or 50)))  # warm-up (allocations, code objects)
     J, g, tf, tb = once(steps)
     if sched is None:  # the schedule of this rollout (bit-identical replay)
         U = inputs.kh_sine_state(torch.tensor(a_np, dtype=torch.float64, device="cuda"), prm).contiguous()
@@ -249,7 +250,8 @@ def main():
     ap.add_argument("--only-fp64", action="store_true", help="skip the FP32-bulk leg")
     ap.add_argument("--adj-n", type=int, default=1024, help="adjoint workload grid (n x n; 0: skip)")
     ap.add_argument("--adj-steps", type=int, default=500)
-    ap.add_argument("--adj-ckpt", type=int, default=50)
+    ap.add_argument("--adj-ckpt", type=int, default=50,
+                    help="checkpoint interval of the checkpointed adjoint figure (the headline keeps all states)")
     ap.add_argument("--poisson-n", type=int, default=1024,
                     help="potential-solver workload grid (n x n; 0: skip)")
     ap.add_argument("--poisson-cpu-iters", type=int, default=200)
@@ -330,21 +332,32 @@ def main():
     adj = None
     if args.adj_n > 0:
         a_np = inputs.kh_sine_amplitudes()
+        # headline: every state kept (3 x 500 states of 32 MiB at 1024^2), no replay
         s64a, J64, g64, tf64, tb64, sched = adjoint_leg(torch, hydro, inputs, args.adj_n, args.adj_steps,
-                                                       args.adj_ckpt, hydro.FP64, a_np)
+                                                       None, hydro.FP64, a_np)
         _, J32, g32, tf32, tb32, _ = adjoint_leg(torch, hydro, inputs, args.adj_n, args.adj_steps,
-                                                 args.adj_ckpt, hydro.FP32_BULK, a_np, sched)
+                                                 None, hydro.FP32_BULK, a_np, sched)
+        # the same gradient with checkpoints (stage states recomputed per segment)
+        _, _, g64c, tf64c, tb64c, _ = adjoint_leg(torch, hydro, inputs, args.adj_n, args.adj_steps,
+                                                  args.adj_ckpt, hydro.FP64, a_np, sched)
+        _, _, _, tf32c, tb32c, _ = adjoint_leg(torch, hydro, inputs, args.adj_n, args.adj_steps,
+                                               args.adj_ckpt, hydro.FP32_BULK, a_np, sched)
         comps = [0, 17, 63]
         fd = fd_check(torch, inputs, s64a, a_np, sched, comps)
         fd_err = float(np.max(np.abs(fd - g64[comps]) / np.abs(g64).max()))
-        adj = {"workload": f"kh_sine_{args.adj_n}x{args.adj_n}_{args.adj_steps}steps_ckpt{args.adj_ckpt}",
+        adj = {"workload": f"kh_sine_{args.adj_n}x{args.adj_n}_{args.adj_steps}steps",
                "J": J64,
+               "states_kept_gb": 3 * args.adj_steps * 32 * args.adj_n * args.adj_n / 1e9,
                "fwd_ms_fp64": tf64 * 1e3, "bwd_ms_fp64": tb64 * 1e3, "ratio_fp64": tb64 / tf64,
                "fwd_ms_fp32": tf32 * 1e3, "bwd_ms_fp32": tb32 * 1e3, "ratio_fp32": tb32 / tf32,
+               "ckpt_every": args.adj_ckpt,
+               "ratio_fp64_ckpt": tb64c / tf64c, "ratio_fp32_ckpt": tb32c / tf32c,
+               "ckpt_grad_bitwise_equal": bool(np.array_equal(g64c, g64)),
                "fd_components": comps, "fd_rel_err_fp64": fd_err,
                "grad_rel_err_fp32_vs_fp64": float(np.linalg.norm(g32 - g64) / np.linalg.norm(g64))}
         log(f"adjoint: fp64 ratio {adj['ratio_fp64']:.2f} (fwd {tf64 * 1e3:.1f} ms, bwd {tb64 * 1e3:.1f} ms), "
-            f"fp32 ratio {adj['ratio_fp32']:.2f}, FD rel err {fd_err:.2e}, "
+            f"fp32 ratio {adj['ratio_fp32']:.2f}; checkpointed every {args.adj_ckpt}: "
+            f"{adj['ratio_fp64_ckpt']:.2f} / {adj['ratio_fp32_ckpt']:.2f}; FD rel err {fd_err:.2e}, "
             f"fp32 grad rel err {adj['grad_rel_err_fp32_vs_fp64']:.2e}")
 
     pois = None

@@ -8,7 +8,10 @@ the segment from its checkpoint with the recorded schedule (bit-identical to
 the forward) through ``hydro_step_save``, keeping the state at the start of
 every step and its two Runge-Kutta stage states, and then applies
 ``hydro_step_vjp_saved`` step by step.  Memory: nsteps / ckpt_every
-checkpoints plus 3 * ckpt_every states.
+checkpoints plus 3 * ckpt_every states.  With ``ckpt_every=None`` the forward
+runs ``hydro_run_save`` and keeps all 3 * nsteps states (a 1024^2, 500-step
+rollout: 50 GB, a sixth of the device's memory), and the backward pass is
+the step adjoints alone.
 
 The gradient is that of the discrete map with the schedule (dt and alpha of
 every stage) held at its recorded values: those come from maxima over the
@@ -23,22 +26,30 @@ from . import hydro
 
 class HydroRollout(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, U0, solver: "hydro.Solver", nsteps: int, ckpt_every: int = 50):
-        if ckpt_every < 1:
-            raise ValueError("ckpt_every must be >= 1")
+    def forward(ctx, U0, solver: "hydro.Solver", nsteps: int, ckpt_every=50):
         U = U0.detach().clone().contiguous()
         dts = torch.empty(max(nsteps, 1), dtype=torch.float64, device=U.device)
         als = torch.empty((max(nsteps, 1), 6), dtype=torch.float64, device=U.device)
+        ctx.solver = solver
+        ctx.nsteps = nsteps
+        ctx.sched = (dts[:nsteps], als[:nsteps])
+        if ckpt_every is None:
+            # keep every step's start and stage states: no replay in backward
+            states = torch.empty((max(nsteps, 1), 3) + tuple(U.shape), dtype=torch.float64, device=U.device)
+            if nsteps > 0:
+                solver.run_save(U, nsteps, states[:nsteps], dts[:nsteps], als[:nsteps])
+            ctx.states = states
+            ctx.ckpt_every = None
+            return U
+        if ckpt_every < 1:
+            raise ValueError("ckpt_every must be >= 1 (or None to keep every state)")
         ckpts = []
         for s0 in range(0, nsteps, ckpt_every):
             k = min(ckpt_every, nsteps - s0)
             ckpts.append(U.clone())
             solver.run_into(U, k, dts[s0:s0 + k], als[s0:s0 + k])
-        ctx.solver = solver
-        ctx.nsteps = nsteps
         ctx.ckpt_every = ckpt_every
         ctx.ckpts = ckpts
-        ctx.sched = (dts[:nsteps], als[:nsteps])
         return U
 
     @staticmethod
@@ -49,6 +60,12 @@ class HydroRollout(torch.autograd.Function):
         als_h = als.cpu().numpy().reshape(-1, 2, 3).transpose(0, 2, 1)  # [n][stage][ax, ay]
         lam = gU.detach().contiguous().clone()
         nxt = torch.empty_like(lam)
+        if ctx.ckpt_every is None:
+            st = ctx.states
+            for i in range(ctx.nsteps - 1, -1, -1):
+                solver.step_vjp_saved(st[i, 0], st[i, 1], st[i, 2], dts_h[i], als_h[i], lam, out=nxt)
+                lam, nxt = nxt, lam
+            return lam, None, None, None
         kmax = min(ctx.ckpt_every, ctx.nsteps)
         # per step of a segment: its start state and its two stage states
         pool = [[torch.empty_like(lam) for _ in range(3)] for _ in range(kmax)]
@@ -70,7 +87,9 @@ class HydroRollout(torch.autograd.Function):
 
 
 def rollout(U0, solver, nsteps, ckpt_every=50):
-    """Differentiable nsteps-step rollout of U0 (float64, (4, ny, nx), on the solver's device)."""
+    """Differentiable nsteps-step rollout of U0 (float64, (4, ny, nx), on the solver's device).
+    ckpt_every=None keeps all 3 * nsteps states (96 B per cell and step) and the
+    backward pass replays nothing."""
     return HydroRollout.apply(U0, solver, nsteps, ckpt_every)
 
 

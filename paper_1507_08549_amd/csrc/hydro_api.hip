@@ -348,6 +348,46 @@ int hydro_run(hydro_ctx* c, double* U, int32_t nsteps, double t_end, double* t_i
   return c->h_ctl->steps;
 }
 
+int hydro_run_save(hydro_ctx* c, double* U, int32_t nsteps, double t_end, double* t_io, double* dt_rec,
+                   double* alpha_rec, double* states) {
+  if (!c || !U || !states || nsteps < 0) return HYDRO_E_INVALID;
+  DeviceGuard dg(c->device);
+  if (!dg.ok) return HYDRO_E_DEVICE;
+  const size_t n4 = 4 * c->n;
+  auto S = [&](int k, int s) { return states + ((size_t)k * 3 + (size_t)s) * n4; };
+  const double t0 = t_io ? *t_io : 0.0;
+  hipLaunchKernelGGL(set_ctl_kernel, dim3(1), dim3(64), 0, c->stream, c->ctl, t0);
+  HY_CHECK(hipGetLastError());
+  if (nsteps > 0) HY_CHECK(hipMemcpyAsync(S(0, 0), U, n4 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  HY_CHECK(hy::launch_alpha_reduce(c->g, U, c->ctl, 0, c->apart, c->stream));
+  for (int k = 0; k < nsteps; ++k) {
+    for (int s = 0; s < 3; ++s) {
+      hy::StageArgs a{};
+      a.g = c->g;
+      a.U0 = S(k, 0);
+      a.V = S(k, s);
+      a.W = s < 2 ? S(k, s + 1) : (k + 1 < nsteps ? S(k + 1, 0) : U);
+      a.b = kStageWeight[s];
+      a.stage = s;
+      a.ctl = c->ctl;
+      a.dt_mode = 1;
+      a.t_end = t_end;
+      a.dt_rec = dt_rec ? dt_rec + k : nullptr;
+      a.alpha_rec = alpha_rec ? alpha_rec + 6 * (size_t)k : nullptr;
+      HY_CHECK(launch_stage(c, a));
+    }
+  }
+  int rc = read_flag(c, false);
+  if (t_io) *t_io = c->h_ctl->t;
+  const int steps = c->h_ctl->steps;
+  if (steps > 0 && steps < nsteps) {  // stopped at t_end: the last state taken is the start of step `steps`
+    HY_CHECK(hipMemcpyAsync(U, S(steps, 0), n4 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HY_CHECK(hipStreamSynchronize(c->stream));
+  }
+  if (rc) return rc;
+  return steps;
+}
+
 int hydro_rhs(hydro_ctx* c, const double* V, double ax, double ay, double* L) {
   if (!c || !V || !L || V == L) return HYDRO_E_INVALID;
   DeviceGuard dg(c->device);

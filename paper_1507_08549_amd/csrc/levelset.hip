@@ -31,8 +31,8 @@
 //                        its right edge, its upper edge), one atomic per
 //                        wavefront to reserve space (the order of the points is
 //                        not fixed; nothing downstream depends on it);
-//  ls_distance           nearest-point search and blend: 256 corners per
-//                        workgroup, four per work item; points streamed through
+//  ls_distance           nearest-point search and blend: 32 x 16 corners per
+//                        workgroup, two per work item; points streamed through
 //                        LDS.  The minimum is taken over squared distances and
 //                        rooted once (the square root is monotone and correctly
 //                        rounded, so this equals the minimum of the roots).
@@ -280,7 +280,10 @@ __global__ __launch_bounds__(LS_THREADS) void ls_front_kernel(LsArgs a, double* 
 
 // Distance and blend.  Corner tile 64 x 16 (four corners per work item, rows
 // ty, ty+4, ty+8, ty+12); points staged through LDS in chunks.
-constexpr int DTX = 64, DTY = 16, DCH = 512;
+constexpr int DTX = 32, DTY = 16, DCH = 512;
+constexpr int DRS = LS_THREADS / DTX;  // row stride of a work item's corners
+constexpr int DR = DTY / DRS;          // corners per work item
+static_assert(DR * DRS == DTY && LS_THREADS % DTX == 0, "distance tile shape");
 
 __global__ __launch_bounds__(LS_THREADS) void ls_distance_kernel(LsArgs a, const double* pts, double* dist) {
   __shared__ double P[2][DCH];
@@ -319,10 +322,10 @@ __global__ __launch_bounds__(LS_THREADS) void ls_distance_kernel(LsArgs a, const
   const int tx = tid % DTX, ty = tid / DTX;
   const int i = i0 + tx;
   const double x = a.xlo + (double)i * a.dx;
-  double yv[4], best[4];
+  double yv[DR], best[DR];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    yv[r] = a.ylo + (double)(j0 + ty + 4 * r) * a.dy;
+  for (int r = 0; r < DR; ++r) {
+    yv[r] = a.ylo + (double)(j0 + ty + DRS * r) * a.dy;
     best[r] = __builtin_inf();
   }
   for (long long c0 = 0; c0 < np; c0 += DCH) {
@@ -346,7 +349,7 @@ __global__ __launch_bounds__(LS_THREADS) void ls_distance_kernel(LsArgs a, const
     for (int k = 0; k < nk; ++k) {
       const double ex = x - P[0][k];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
+      for (int r = 0; r < DR; ++r) {
         const double ey = yv[r] - P[1][k];
         best[r] = __builtin_fmin(best[r], ex * ex + ey * ey);
       }
@@ -357,8 +360,8 @@ __global__ __launch_bounds__(LS_THREADS) void ls_distance_kernel(LsArgs a, const
   const double w = D / 3.0, d0 = 3.0 * D;
   const double den = 1.0 - tanh(-d0 / w);
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int j = j0 + ty + 4 * r;
+  for (int r = 0; r < DR; ++r) {
+    const int j = j0 + ty + DRS * r;
     if (j >= a.my) continue;
     const size_t kc = (size_t)j * a.mx + i;
     const double d = cr_sqrt(best[r]);

@@ -58,7 +58,7 @@ _lib = None
 
 #: names of the entry points declared in include/hydro.h
 ENTRY_POINTS = ("hydro_create", "hydro_destroy", "hydro_cfl", "hydro_step", "hydro_run",
-                "hydro_rhs", "hydro_step_vjp", "hydro_step_save", "hydro_step_vjp_saved",
+                "hydro_run_save", "hydro_rhs", "hydro_step_vjp", "hydro_step_save", "hydro_step_vjp_saved",
                 "hydro_poisson", "hydro_gravity", "hydro_ls_velocity", "hydro_ls_step", "hydro_ls_front",
                 "hydro_ls_redistance", "hydro_sums", "hydro_check", "hydro_strerror")
 
@@ -84,6 +84,7 @@ def load():
     lib.hydro_cfl.argtypes = [vp, vp, dp]
     lib.hydro_step.argtypes = [vp, vp, ctypes.c_double, ctypes.POINTER(Alpha), ctypes.POINTER(Alpha)]
     lib.hydro_run.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_double, dp, vp, vp]
+    lib.hydro_run_save.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_double, dp, vp, vp, vp]
     lib.hydro_rhs.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double, vp]
     lib.hydro_step_vjp.argtypes = [vp, vp, ctypes.c_double, ctypes.POINTER(Alpha), vp, vp]
     lib.hydro_step_save.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.POINTER(Alpha), vp, vp]
@@ -238,6 +239,21 @@ class Solver:
         rc = self._lib.hydro_run(self._h, self._state(U), int(nsteps), float(t_end), ctypes.byref(tt),
                                  dt_rec.data_ptr(), alpha_rec.data_ptr())
         return self._check(rc, "hydro_run")
+
+    def run_save(self, U, nsteps, states, dt_rec, alpha_rec, t_end=0.0, t0=0.0):
+        """hydro_run_save: as run_into, also filling states (nsteps, 3, 4, ny, nx)
+        with each step's start state and its two stage states.  Returns steps taken."""
+        t = self.torch
+        shape = (nsteps, 3, 4, self.ny, self.nx)
+        for name, x, shp in (("dt_rec", dt_rec, (nsteps,)), ("alpha_rec", alpha_rec, (nsteps, 6)),
+                             ("states", states, shape)):
+            if (not isinstance(x, t.Tensor) or x.dtype != t.float64 or x.device != self.device
+                    or tuple(x.shape) != shp or not x.is_contiguous()):
+                raise ValueError(f"{name} must be a contiguous float64 {shp} tensor on {self.device}")
+        tt = ctypes.c_double(float(t0))
+        rc = self._lib.hydro_run_save(self._h, self._state(U), int(nsteps), float(t_end), ctypes.byref(tt),
+                                      dt_rec.data_ptr(), alpha_rec.data_ptr(), states.data_ptr())
+        return self._check(rc, "hydro_run_save")
 
     def rhs(self, V, ax, ay, out=None):
         L = self.new_state() if out is None else out

@@ -217,3 +217,56 @@ def test_saved_stage_states_reproduce_step_and_vjp(torch, hydro, oracle_mod):
     assert torch.equal(a, b)
     ref = torch_ref.vjp(prm, None, U0, dt, al, lam.cpu().numpy())
     assert _rel_l1(b.cpu().numpy(), ref) <= 1e-11
+
+
+def test_run_save_keeps_every_state(torch, hydro, oracle_mod):
+    """hydro_run_save: the same final state and schedule as hydro_run, each
+    step's start state equal to the oracle's, its stage states equal to what
+    hydro_step_save writes; stopping at t_end leaves the last state in U."""
+    prm, U0 = inputs.kelvin_helmholtz(48, seed=17)
+    prm["bc"] = [R, T, P, P]
+    s = hydro.Solver(prm)
+    n = 7
+    U = _dev(torch, U0)
+    dts = torch.empty(n, dtype=torch.float64, device="cuda")
+    als = torch.empty((n, 6), dtype=torch.float64, device="cuda")
+    st = torch.empty((n, 3, 4, 48, 48), dtype=torch.float64, device="cuda")
+    assert s.run_save(U, n, st, dts, als) == n
+    V = _dev(torch, U0)
+    k, _, d2, a2 = s.run(V, n, record=True)
+    assert k == n and torch.equal(U, V) and torch.equal(dts, d2)
+    assert torch.equal(als.reshape(n, 2, 3).transpose(1, 2), a2)  # run() returns [step][stage][ax, ay]
+    o = oracle_mod.Oracle(prm)
+    W = U0.copy()
+    dth = dts.cpu().numpy()
+    alh = als.cpu().numpy().reshape(-1, 2, 3).transpose(0, 2, 1)
+    U1 = torch.empty_like(V)
+    U2 = torch.empty_like(V)
+    for i in range(n):
+        assert np.array_equal(st[i, 0].cpu().numpy(), W), i
+        s.step_save(_dev(torch, W), dth[i], alh[i], U1, U2)
+        assert torch.equal(st[i, 1], U1) and torch.equal(st[i, 2], U2), i
+        W, _ = o.step(W, dth[i], alh[i])
+    # stop at t_end after 3 steps: U holds the state after step 3
+    t3 = float(dth[:3].sum())
+    U = _dev(torch, U0)
+    st.zero_()
+    assert s.run_save(U, n, st, dts, als, t_end=t3) == 3
+    assert torch.equal(U, st[3, 0])
+
+
+def test_rollout_keeping_all_states_equals_checkpointed(torch, hydro):
+    """ckpt_every=None (no replay) gives the checkpointed rollout's gradient bit
+    for bit: the replay reproduces the forward's stage states exactly."""
+    from paper_1507_08549_amd.autograd import rollout
+    n, K, steps = 48, 8, 17
+    prm = inputs.kh_sine_params(n)
+    a_np = inputs.kh_sine_amplitudes(K, seed=5) * 20.0
+    s = hydro.Solver(prm)
+    grads = []
+    for ck in (None, 5, 17):
+        a = torch.tensor(a_np, dtype=torch.float64, device="cuda", requires_grad=True)
+        UN = rollout(inputs.kh_sine_state(a, prm), s, steps, ckpt_every=ck)
+        (g,) = torch.autograd.grad(_objective(torch, UN, prm), a)
+        grads.append(g)
+    assert torch.equal(grads[0], grads[1]) and torch.equal(grads[0], grads[2])

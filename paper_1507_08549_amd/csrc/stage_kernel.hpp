@@ -296,9 +296,11 @@ __device__ __forceinline__ void store_roe_inputs(const R U[4], R gamma, R gm1, R
   Q[3 * np + k] = cr_div(U[3] + w.p, U[0]);
 }
 
-template <typename R, int TX, int TY, bool HASY, bool CHAR = false>
-__global__ __launch_bounds__(TX* TY) void stage_kernel(StageArgs a) {
-  constexpr int NT = TX * TY;
+template <typename R, int TX, int TY, bool HASY, bool CHAR = false, int NTH = TX * TY>
+__global__ __launch_bounds__(NTH) void stage_kernel(StageArgs a) {
+  constexpr int NT = NTH;       // work items
+  constexpr int NCELL = TX * TY;  // cells of the tile (the first NCELL work items own one each)
+  static_assert(NT % NCELL == 0 && (!CHAR || NT == NCELL), "work items per tile");
   constexpr int GY = HASY ? NG : 0;
   constexpr int TXP = TX + 2 * NG;
   constexpr int TYP = TY + 2 * GY;
@@ -393,7 +395,8 @@ __global__ __launch_bounds__(TX* TY) void stage_kernel(StageArgs a) {
   };
 
   const int tx = tid % TX, ty = tid / TX;
-  R D[4];
+  const bool owner = tid < NCELL;
+  R D[4] = {R(0), R(0), R(0), R(0)};
 
   // ---- 1. x sweep: split fluxes of the tile rows and their x-halo points
   // (read straight from L2 into registers; only the split fluxes live in LDS),
@@ -461,9 +464,11 @@ __global__ __launch_bounds__(TX* TY) void stage_kernel(StageArgs a) {
     }
     __syncthreads();
     const R idx = (R)g.idx;
+    if (owner) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
-      D[c] = (sFh[c * NFX + ty * (TX + 1) + tx + 1] - sFh[c * NFX + ty * (TX + 1) + tx]) * idx;
+      for (int c = 0; c < 4; ++c)
+        D[c] = (sFh[c * NFX + ty * (TX + 1) + tx + 1] - sFh[c * NFX + ty * (TX + 1) + tx]) * idx;
+    }
   }
 
   // ---- 2. y sweep (skipped in the 1D limit), same pattern
@@ -530,14 +535,16 @@ __global__ __launch_bounds__(TX* TY) void stage_kernel(StageArgs a) {
     }
     __syncthreads();
     const R idy = (R)g.idy;
+    if (owner) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
-      Dy[c] = (sFh[c * NFY + (ty + 1) * TX + tx] - sFh[c * NFY + ty * TX + tx]) * idy;
+      for (int c = 0; c < 4; ++c)
+        Dy[c] = (sFh[c * NFY + (ty + 1) * TX + tx] - sFh[c * NFY + ty * TX + tx]) * idy;
+    }
   }
 
   // ---- 3. per cell: sources, L, stage combination, floors, check, maxima
   const int I = i0 + tx, J = j0 + ty;
-  const bool act = I < g.nx && J < g.ny;
+  const bool act = owner && I < g.nx && J < g.ny;
   double amax = 0.0, bmax = 0.0, smax = 0.0;
   bool bad = false;
   if (act) {

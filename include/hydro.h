@@ -153,8 +153,8 @@ int hydro_run(hydro_ctx* ctx, double* U, int32_t nsteps, double t_end, double* t
  * makes the other way; 96 B per cell and step).  states: device
  * [nsteps][3][4][ny][nx]: [k][0] the state at the start of step k, [k][1] and
  * [k][2] its two Runge-Kutta stage states (as hydro_step_save writes them);
- * entries of steps not taken (t_end reached) are left as they are.  U: in, the
- * initial state; out, the final one.  Other arguments, return value and
+ * entries of steps not taken (t_end reached) are left as they are; it must
+ * not overlap U.  U: in, the initial state; out, the final one.  Other arguments, return value and
  * synchronisation as hydro_run. */
 int hydro_run_save(hydro_ctx* ctx, double* U, int32_t nsteps, double t_end, double* t_io,
                    double* dt_rec, double* alpha_rec, double* states);

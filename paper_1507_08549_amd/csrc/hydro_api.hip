@@ -350,7 +350,7 @@ int hydro_run(hydro_ctx* c, double* U, int32_t nsteps, double t_end, double* t_i
 
 int hydro_run_save(hydro_ctx* c, double* U, int32_t nsteps, double t_end, double* t_io, double* dt_rec,
                    double* alpha_rec, double* states) {
-  if (!c || !U || !states || nsteps < 0) return HYDRO_E_INVALID;
+  if (!c || !U || !states || states == U || nsteps < 0) return HYDRO_E_INVALID;
   DeviceGuard dg(c->device);
   if (!dg.ok) return HYDRO_E_DEVICE;
   const size_t n4 = 4 * c->n;

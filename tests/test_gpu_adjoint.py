@@ -247,6 +247,11 @@ def test_run_save_keeps_every_state(torch, hydro, oracle_mod):
         s.step_save(_dev(torch, W), dth[i], alh[i], U1, U2)
         assert torch.equal(st[i, 1], U1) and torch.equal(st[i, 2], U2), i
         W, _ = o.step(W, dth[i], alh[i])
+    with pytest.raises(ValueError):
+        s.run_save(U, n, st[:2], dts, als)
+    with pytest.raises(hydro.HydroError):  # the state buffer may not be U itself
+        s._check(s._lib.hydro_run_save(s._h, U.data_ptr(), 1, 0.0, None, None, None, U.data_ptr()),
+                 "hydro_run_save")
     # stop at t_end after 3 steps: U holds the state after step 3
     t3 = float(dth[:3].sum())
     U = _dev(torch, U0)

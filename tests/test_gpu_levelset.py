@@ -206,3 +206,58 @@ def test_ls_flame_front_full_size(torch, hydro, oracle_mod):
         _same(got, ls.distance_at(want, js, is_), "sampled distances")
     finally:
         s.close()
+
+
+def test_ls_front_capacity_and_optional_distance(torch, hydro, oracle_mod):
+    """A capacity below the count copies that many points and still reports the
+    count; re-distancing without a distance output gives the same field."""
+    prm = inputs.make_params(40, 30, 0.0, 1.0, 0.0, 0.75, [T, T, T, T], 1.4)
+    S, _ = _field(prm, 21)
+    s = hydro.Solver(prm)
+    try:
+        Sd = _dev(torch, S)
+        allp = s.ls_front(Sd).cpu().numpy()
+        few = s.ls_front(Sd, cap=5).cpu().numpy()
+        assert len(few) == 5 and len(allp) == len(oracle_mod.LevelSet(prm).front(S)) > 5
+        assert {tuple(p) for p in few} <= {tuple(p) for p in allp}
+        A, B = _dev(torch, S), _dev(torch, S)
+        d = torch.zeros_like(A)
+        assert s.ls_redistance(A, d) == s.ls_redistance(B) == len(allp)
+        assert torch.equal(A, B)
+    finally:
+        s.close()
+
+
+def test_ls_coupled_to_the_flow(torch, hydro, oracle_mod):
+    """The front carried by the fluid: per round one hydro step, the corner
+    velocity of the new state, one level-set step with a flame speed; the GPU
+    and the oracle stay bit-identical through three rounds, then one
+    re-distancing agrees to the blend's tolerance."""
+    prm, U0 = inputs.kelvin_helmholtz(64, seed=9)
+    x, y = inputs.corners(prm)
+    X, Y = np.meshgrid(x, y)
+    S0 = 0.2 - np.sqrt((X - 0.5) ** 2 + (Y - 0.4) ** 2)
+    o, ls = oracle_mod.Oracle(prm), oracle_mod.LevelSet(prm)
+    s = hydro.Solver(prm)
+    try:
+        U, S = _dev(torch, U0), _dev(torch, S0)
+        vel = torch.empty((2, 65, 65), dtype=torch.float64, device="cuda")
+        Uo, So = U0.copy(), S0.copy()
+        for k in range(3):
+            dt = o.cfl(Uo)
+            assert s.cfl(U) == dt
+            s.step(U, dt)
+            Uo, _ = o.step(Uo, dt)
+            s.ls_velocity(U, out=vel)
+            vo = ls.corner_velocity(Uo)
+            _same(vel.cpu().numpy(), vo, f"corner velocity, round {k}")
+            s.ls_step(S, vel, 0.05, dt)
+            So = ls.step(So, vo, 0.05, dt)
+            _same(S.cpu().numpy(), So, f"S, round {k}")
+        d = torch.zeros_like(S)
+        s.ls_redistance(S, d)
+        Sw, dw, _ = ls.redistance(So)
+        _same(d.cpu().numpy(), dw, "distance")
+        assert np.all(np.abs(S.cpu().numpy() - Sw) <= 4e-15 * (np.abs(So) + dw))
+    finally:
+        s.close()

@@ -208,6 +208,8 @@ def test_poisson_rejects_other_geometries(torch, hydro):
         try:
             with pytest.raises(hydro.HydroError):
                 s.poisson(rho, phi, 1.0, 1.0)
+            with pytest.raises(hydro.HydroError):
+                s.gravity_from_potential(phi, 1.0, 1.0)
         finally:
             s.close()
     s = hydro.Solver(_quarter_params(16, 16, 1.0, 1.0))

@@ -52,3 +52,23 @@ def test_workload_shapes_and_seeds():
     assert U.shape == (4, 128, 32) and prm["gy"] == -0.1
     prm, U = inputs.sod(400)
     assert U.shape == (4, 1, 400)
+
+
+def test_flame_front_workload():
+    """Corner grid, seeded and reproducible; ash (S > 0) inside the perturbed
+    circle around (0.5, 0.75), fuel outside; the single vortex is divergence
+    free on the corners to second order and vanishes on the walls."""
+    prm, S, vel, s_f = inputs.flame_front(64)
+    assert S.shape == (65, 65) and vel.shape == (2, 65, 65) and s_f > 0
+    prm2, S2, vel2, _ = inputs.flame_front(64)
+    assert np.array_equal(S, S2) and np.array_equal(vel, vel2)
+    _, S3, _, _ = inputs.flame_front(64, seed=7)
+    assert not np.array_equal(S, S3)
+    x, y = inputs.corners(prm)
+    assert x[0] == 0.0 and x[-1] == 1.0 and y[-1] == 1.0
+    assert S[48, 32] > 0 and S[5, 5] < 0 and S[60, 60] < 0   # centre (0.5, 0.75) burnt, corners fuel
+    # walls: normal velocity zero (u = 0 on x = 0, 1; v = 0 on y = 0, 1)
+    assert np.abs(vel[0][:, 0]).max() < 1e-15 and np.abs(vel[1][0, :]).max() < 1e-15
+    h = 1.0 / 64
+    div = (vel[0][1:-1, 2:] - vel[0][1:-1, :-2]) / (2 * h) + (vel[1][2:, 1:-1] - vel[1][:-2, 1:-1]) / (2 * h)
+    assert np.abs(div).max() < 0.01

@@ -14,8 +14,10 @@ roofline of the stage kernel, the oracle's own rate on the host cores, and the
 adjoint workload (sine-mode shear layer, 1024^2, 500 steps: backward/forward
 time ratio in FP64 and FP32 keeping every state, and with checkpoints every
 50 steps; central-difference check; FP32-vs-FP64 gradient error), and the potential solver on the polytrope
-density (1024^2, red-black over-relaxation to the relative change 1e-8), and
-the level-set flame front (1025^2 corners: advection step and re-distancing).
+density (1024^2, red-black over-relaxation to the relative change 1e-8), the
+level-set flame front (1025^2 corners: advection step and re-distancing), the
+step at 1024^2, 2048^2 and 4096^2 (states beyond the last-level cache), and
+two achievable-peak probes (FP64 fma rate, device copy).
 """
 from __future__ import annotations
 
@@ -56,9 +58,9 @@ POISSON_BYTES_PER_CELL_ITER = 8 * 4
 STAGE_TRAFFIC = {
     "sources": ["paper_1507_08549_amd/csrc/stage_kernel.hpp", "paper_1507_08549_amd/csrc/ieee.hpp",
                 "paper_1507_08549_amd/csrc/stage_fp64.hip", "paper_1507_08549_amd/csrc/hydro_internal.hpp"],
-    "sha256": "4e710615df86899669f2016dc0ad584dcf355a0274315095b874dcf9bbfb3492",
+    "sha256": "1c02f0f703ec9cf6dd6c1b9722c93fa3f4a6896efe183f58100de6d9c071ed49",
     "n": 512,
-    "bytes_per_launch": (15.183 + 8.489) * 1e6,
+    "bytes_per_launch": (15.180 + 8.489) * 1e6,
 }
 
 
@@ -142,6 +144,54 @@ def fd_check(torch, inputs, s, a_np, sched, comps, h=1e-7):
         e[k] = h
         out.append((J_of(a_np + e) - J_of(a_np - e)) / (2 * h))
     return np.array(out)
+
+
+def probes(torch, solver):
+    """Achievable-peak references: the FP64 fma rate (library probe kernel) and
+    a 1 GiB device-to-device copy (read + written bytes per second)."""
+    fma = solver.probe_fma(20000)
+    nel = (1 << 30) // 8
+    src = torch.ones(nel, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 5 * 2 * (1 << 30) / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del src, dst
+    out = {"fp64_fma_tflops": fma / 1e12, "fp64_fma_frac_of_peak": fma / 1e12 / PEAK_FP64_VALU_TFLOPS,
+           "copy_gbs": gbs, "copy_frac_of_peak": gbs / PEAK_HBM_GBS}
+    log(f"probes: fp64 fma {out['fp64_fma_tflops']:.1f} TFLOP/s, copy {gbs:.0f} GB/s")
+    return out
+
+
+def sweep_leg(torch, hydro, inputs, sizes, steps):
+    """The FP64 step at sizes whose states no longer fit in the 256 MB
+    last-level cache: cell-updates/s and the algorithmic HBM rate."""
+    out = []
+    for n in sizes:
+        prm, U0 = inputs.kelvin_helmholtz(n, seed=2)
+        s = hydro.Solver(prm)
+        U = torch.tensor(U0, dtype=torch.float64, device="cuda")
+        del U0
+        s.run(U, 10)
+        t, _ = timed_run(torch, s, U, steps)
+        r = {"n": n, "steps": steps, "ms_per_step": t * 1e3 / steps,
+             "cell_updates_per_s": n * n * steps / t,
+             "hbm_gbs_algorithmic": BYTES_PER_CELL_STEP * n * n * steps / t / 1e9,
+             "state_mb": 32 * n * n / 1e6}
+        r["hbm_frac"] = r["hbm_gbs_algorithmic"] / PEAK_HBM_GBS
+        log(f"sweep {n}^2: {r['cell_updates_per_s']:.3e} cell-updates/s, {r['hbm_gbs_algorithmic']:.0f} GB/s")
+        out.append(r)
+        s.close()
+        del U
+        torch.cuda.empty_cache()
+    return out
 
 
 def poisson_leg(torch, hydro, inputs, n, cpu_iters):
@@ -257,6 +307,10 @@ def main():
     ap.add_argument("--poisson-cpu-iters", type=int, default=200)
     ap.add_argument("--ls-n", type=int, default=1024, help="level-set workload cells per side (0: skip)")
     ap.add_argument("--ls-steps", type=int, default=20)
+    ap.add_argument("--sweep", type=str, default="1024,2048,4096",
+                    help="grid sizes of the out-of-cache sweep (comma separated; empty: skip)")
+    ap.add_argument("--sweep-steps", type=int, default=200)
+    ap.add_argument("--no-probes", action="store_true", help="skip the fma-rate and copy probes")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB three times (a known-size "
                          "kernel for calibrating the profiler's HBM byte counters)")
@@ -360,6 +414,11 @@ def main():
             f"{adj['ratio_fp64_ckpt']:.2f} / {adj['ratio_fp32_ckpt']:.2f}; FD rel err {fd_err:.2e}, "
             f"fp32 grad rel err {adj['grad_rel_err_fp32_vs_fp64']:.2e}")
 
+    prb = None if args.no_probes else probes(torch, s64)
+    sweep = None
+    if args.sweep:
+        sweep = sweep_leg(torch, hydro, inputs, [int(v) for v in args.sweep.split(",") if v], args.sweep_steps)
+
     pois = None
     if args.poisson_n > 0:
         pois = poisson_leg(torch, hydro, inputs, args.poisson_n,
@@ -394,6 +453,8 @@ def main():
         "cpu_baseline": cpu,
         "fp32_bulk": fp32,
         "adjoint": adj,
+        "probes": prb,
+        "sweep": sweep,
         "poisson": pois,
         "levelset": lset,
     }

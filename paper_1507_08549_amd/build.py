@@ -28,6 +28,7 @@ UNITS = {
     "reduce.hip": ["-ffp-contract=off"],
     "poisson.hip": ["-ffp-contract=off"],
     "levelset.hip": ["-ffp-contract=off"],
+    "probe.hip": [],
     "vjp_fp64.hip": [],
     "vjp_fp32.hip": [],
 }

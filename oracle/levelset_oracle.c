@@ -25,7 +25,8 @@
  *    Hamilton-Jacobi form of WENO5-JS: one-sided derivatives S_x^-/S_x^+ are the
  *    left-/right-biased fifth-order reconstructions (the same weights, epsilon
  *    and evaluation order as the flux reconstruction of the fluid) of the
- *    undivided-then-scaled differences q_m = (S_m - S_{m-1}) / dx, combined by a
+ *    differences q_m = (S_m - S_{m-1}) (1/dx) (times the reciprocal of the
+ *    spacing, formed once), combined by a
  *    global Lax-Friedrichs flux
  *      Hhat = H((p- + p+)/2, (q- + q+)/2) - ax (p+ - p-)/2 - ay (q+ - q-)/2,
  *    ax = max|u| + s_f, ay = max|v| + s_f over all corners; SSP-RK3 in the
@@ -106,10 +107,11 @@ static void pad_corners(const orc_ls_params *q, const double *S, double *pad) {
 /* One-sided WENO derivatives along a line of the padded array: c points at the
  * corner, s is the stride to the next corner, h the spacing. */
 static void one_sided(const double *c, ptrdiff_t s, double h, double eps, double *dm, double *dp) {
-  double qv[6]; /* q_{m} = (S_m - S_{m-1}) / h for m = i-2 .. i+3 */
+  const double ih = 1.0 / h;
+  double qv[6]; /* q_{m} = (S_m - S_{m-1}) * (1/h) for m = i-2 .. i+3 */
   for (int k = 0; k < 6; ++k) {
     const ptrdiff_t m = (ptrdiff_t)(k - 2);
-    qv[k] = (c[m * s] - c[(m - 1) * s]) / h;
+    qv[k] = (c[m * s] - c[(m - 1) * s]) * ih;
   }
   *dm = orc_weno5(qv[0], qv[1], qv[2], qv[3], qv[4], eps);
   *dp = orc_weno5(qv[5], qv[4], qv[3], qv[2], qv[1], eps);

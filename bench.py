@@ -23,6 +23,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -194,6 +195,43 @@ def sweep_leg(torch, hydro, inputs, sizes, steps):
     return out
 
 
+def configs_leg(torch, hydro, inputs):
+    """The other workloads at their full lengths, FP64 and FP32-bulk: rates, the
+    FP32 form's relative L1 density error against the FP64 path (which matches
+    the oracle bit for bit on every prefix the tests check), and the
+    polytrope's equilibrium drift (max |v| / c_center and the L1 density change
+    after 1000 steps; no exact value exists, the scheme is not well balanced)."""
+    cases = [("kelvin_helmholtz_512x512_2000steps", lambda: inputs.kelvin_helmholtz(512, seed=2) + (None,), 2000),
+             ("rayleigh_taylor_256x1024_5000steps", lambda: inputs.rayleigh_taylor() + (None,), 5000),
+             ("polytrope_1024x1024_1000steps", lambda: inputs.polytrope(1024), 1000)]
+    out = []
+    for name, make, steps in cases:
+        prm, U0, grav = make()
+        g = None if grav is None else torch.tensor(grav, dtype=torch.float64, device="cuda")
+        res = {"workload": name}
+        fin = {}
+        for prec, key in ((hydro.FP64, "fp64"), (hydro.FP32_BULK, "fp32")):
+            s = hydro.Solver(prm, gravity=g, precision=prec)
+            U = torch.tensor(U0, dtype=torch.float64, device="cuda")
+            t, _ = timed_run(torch, s, U, steps)
+            res[f"{key}_cell_updates_per_s"] = prm["nx"] * prm["ny"] * steps / t
+            fin[key] = U
+            s.close()
+        d = (fin["fp32"][0] - fin["fp64"][0]).abs().sum() / fin["fp64"][0].abs().sum()
+        res["fp32_l1_rel_density_err_vs_fp64"] = float(d)
+        if grav is not None:
+            U = fin["fp64"]
+            rho0 = torch.tensor(U0[0], dtype=torch.float64, device="cuda")
+            vmag = torch.sqrt(U[1] ** 2 + U[2] ** 2) / U[0]
+            dense = rho0 > 1e-3
+            res["drift_l1_rel_density"] = float((U[0] - rho0).abs().sum() / rho0.abs().sum())
+            res["drift_max_speed_over_c_center_dense"] = float(vmag[dense].max() / math.sqrt(4.0 / 3.0))
+        log(f"config {name}: fp64 {res['fp64_cell_updates_per_s']:.3e}, fp32 {res['fp32_cell_updates_per_s']:.3e} "
+            f"cell-updates/s, fp32 L1 err {res['fp32_l1_rel_density_err_vs_fp64']:.2e}")
+        out.append(res)
+    return out
+
+
 def poisson_leg(torch, hydro, inputs, n, cpu_iters):
     """Potential of the n = 3 polytrope's density from a zero start to the
     relative change 1e-8 with the near-optimal over-relaxation factor."""
@@ -311,6 +349,9 @@ def main():
                     help="grid sizes of the out-of-cache sweep (comma separated; empty: skip)")
     ap.add_argument("--sweep-steps", type=int, default=200)
     ap.add_argument("--no-probes", action="store_true", help="skip the fma-rate and copy probes")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the full-length runs of the other workloads (shear layer 2000 steps, "
+                         "heavy-over-light layer 5000, polytrope 1000)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB three times (a known-size "
                          "kernel for calibrating the profiler's HBM byte counters)")
@@ -419,6 +460,8 @@ def main():
     if args.sweep:
         sweep = sweep_leg(torch, hydro, inputs, [int(v) for v in args.sweep.split(",") if v], args.sweep_steps)
 
+    cfgs = None if args.no_configs else configs_leg(torch, hydro, inputs)
+
     pois = None
     if args.poisson_n > 0:
         pois = poisson_leg(torch, hydro, inputs, args.poisson_n,
@@ -453,6 +496,7 @@ def main():
         "cpu_baseline": cpu,
         "fp32_bulk": fp32,
         "adjoint": adj,
+        "configs": cfgs,
         "probes": prb,
         "sweep": sweep,
         "poisson": pois,

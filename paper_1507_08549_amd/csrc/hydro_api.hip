@@ -590,6 +590,8 @@ hy::LsArgs ls_args(const hydro_ctx* c) {
   a.ylo = c->p.ylo;
   a.dx = c->g.dx;
   a.dy = c->g.dy;
+  a.idx = c->g.idx;  // 1.0 / dx
+  a.idy = c->g.idy;
   a.eps = c->p.weno_eps;
   a.lc = c->ls_ctl;
   return a;

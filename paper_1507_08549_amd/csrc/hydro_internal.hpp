@@ -129,7 +129,7 @@ struct LsCtl {
 struct LsArgs {
   int mx, my;          // corners per row / column (nx + 1, ny + 1)
   int bc[4];           // fluid codes: 0 periodic, 1 transmissive (linear extrapolation), 2 reflecting
-  double xlo, ylo, dx, dy, eps;
+  double xlo, ylo, dx, dy, idx, idy, eps;  // idx = 1 / dx, idy = 1 / dy
   double s_f, dt, b;   // flame speed, time step, stage weight
   const double* S0;    // step input
   const double* V;     // stage input (front search: the field)

@@ -25,7 +25,8 @@
 //                        sub-slots (bit patterns of non-negative doubles order
 //                        like the values, so atomicMax on them is exact);
 //  ls_stage              one RK stage: 32 x 8 corner tile with a 3-corner halo
-//                        in LDS, the one-sided differences once per edge in LDS,
+//                        in LDS, the one-sided differences (times 1/spacing)
+//                        once per edge in LDS,
 //                        four reconstructions per corner;
 //  ls_front              front points, one work item per corner (its zero test,
 //                        its right edge, its upper edge), one atomic per
@@ -168,11 +169,11 @@ __global__ __launch_bounds__(LS_THREADS) void ls_stage_kernel(LsArgs a) {
   __syncthreads();
   for (int k = tid; k < LTY * (LTX + 5); k += LS_THREADS) {
     const int r = k / (LTX + 5), e = k % (LTX + 5);
-    QX[r][e] = cr_div(T[r + 3][e + 1] - T[r + 3][e], a.dx);
+    QX[r][e] = (T[r + 3][e + 1] - T[r + 3][e]) * a.idx;
   }
   for (int k = tid; k < (LTY + 5) * LTX; k += LS_THREADS) {
     const int e = k / LTX, c = k % LTX;
-    QY[e][c] = cr_div(T[e + 1][c + 3] - T[e][c + 3], a.dy);
+    QY[e][c] = (T[e + 1][c + 3] - T[e][c + 3]) * a.idy;
   }
   double mu, mv;
   read_amax(a.lc, sh, mu, mv);  // contains a barrier

@@ -44,6 +44,8 @@ struct Geom {
 // different workgroups do not queue on one address; a reader takes the max
 // over the sub-slots (one wavefront, NSUB = 64 lanes).
 constexpr int NSUB = 64;
+// Devices per process for which per-device launch facts are cached.
+constexpr int MAX_DEVICES = 16;
 struct Ctl {
   double dt;       // time step of the current step (device-computed mode)
   double t;        // time reached
@@ -73,6 +75,7 @@ struct StageArgs {
   double* dt_rec;     // device mode: this step's record, or nullptr
   double* alpha_rec;  // [6] for this step (ax[3], ay[3]), or nullptr
   int rhs_only;       // write L(V) to W instead of a stage
+  int prio;           // set by the launcher: all workgroups resident at once
 };
 
 // Launchers (defined next to their kernels).

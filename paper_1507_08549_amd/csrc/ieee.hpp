@@ -38,6 +38,16 @@ __device__ __forceinline__ double cr_div(double a, double b) {
   return __builtin_fabs(t2) < __builtin_fabs(t) ? q2 : q;
 }
 
+// The same for a divisor known to be positive: the true quotient then lies on
+// the side of sign(t) alone.
+__device__ __forceinline__ double cr_div_pos(double a, double b) {
+  const double q = a / b;
+  const double t = __builtin_fma(-q, b, a);
+  const double q2 = ieee_step(q, t);
+  const double t2 = __builtin_fma(-q2, b, a);
+  return __builtin_fabs(t2) < __builtin_fabs(t) ? q2 : q;
+}
+
 __device__ __forceinline__ double cr_sqrt(double x) {
   const double s = __builtin_sqrt(x);
   const double t = __builtin_fma(-s, s, x);

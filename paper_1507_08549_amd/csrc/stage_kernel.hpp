@@ -118,7 +118,7 @@ __device__ __forceinline__ double weno5_face(double p0, double p1, double p2, do
   double np, dp, nm, dm;
   weno5_nd(p0, p1, p2, p3, p4, eps, np, dp);
   weno5_nd(m0, m1, m2, m3, m4, eps, nm, dm);
-  return cr_div(np * dm + nm * dp, dp * dm);
+  return cr_div_pos(np * dm + nm * dp, dp * dm);  // dp, dm > 0: sums of positive weights
 }
 
 __device__ __forceinline__ double lf_fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
@@ -254,6 +254,19 @@ __device__ __forceinline__ bool char_face(const double* F, const double* Q, int 
   return ok;
 }
 
+// Face value of one component from its split-flux stencils in LDS: P points
+// at f+ of the face's fourth-left point, M at f- of the same point, st is the
+// point stride; the face lies between points 2 and 3.
+template <typename R>
+__device__ __forceinline__ R face_value(const R* P, const R* M, int st, R eps) {
+  if constexpr (sizeof(R) == 8)
+    return weno5_face(P[0], P[st], P[2 * st], P[3 * st], P[4 * st], M[5 * st], M[4 * st], M[3 * st],
+                      M[2 * st], M[st], eps);
+  else
+    return weno5(P[0], P[st], P[2 * st], P[3 * st], P[4 * st], eps) +
+           weno5(M[5 * st], M[4 * st], M[3 * st], M[2 * st], M[st], eps);
+}
+
 // Max over the NSUB sub-slots of ring slot s, by wavefront 0, broadcast to the
 // block through LDS.  Every work item of the block must call it.
 __device__ __forceinline__ void read_slot(const Ctl* ctl, int s, double out[3], double* sh) {
@@ -296,11 +309,9 @@ __device__ __forceinline__ void store_roe_inputs(const R U[4], R gamma, R gm1, R
   Q[3 * np + k] = cr_div(U[3] + w.p, U[0]);
 }
 
-template <typename R, int TX, int TY, bool HASY, bool CHAR = false, int NTH = TX * TY>
-__global__ __launch_bounds__(NTH) void stage_kernel(StageArgs a) {
-  constexpr int NT = NTH;       // work items
-  constexpr int NCELL = TX * TY;  // cells of the tile (the first NCELL work items own one each)
-  static_assert(NT % NCELL == 0 && (!CHAR || NT == NCELL), "work items per tile");
+template <typename R, int TX, int TY, bool HASY, bool CHAR = false>
+__global__ __launch_bounds__(TX * TY) void stage_kernel(StageArgs a) {
+  constexpr int NT = TX * TY;  // work items, one per cell of the tile
   constexpr int GY = HASY ? NG : 0;
   constexpr int TXP = TX + 2 * NG;
   constexpr int TYP = TY + 2 * GY;
@@ -326,6 +337,65 @@ __global__ __launch_bounds__(NTH) void stage_kernel(StageArgs a) {
   const int tid = threadIdx.x;
   const bool lead = (blockIdx.x == 0 && tid == 0);
 
+  const int ntx = (g.nx + TX - 1) / TX;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int i0 = (tile % ntx) * TX;
+  const int j0 = (tile / ntx) * TY;
+  const size_t n = (size_t)g.nx * g.ny;
+  const R gamma = (R)g.gamma, gm1 = (R)g.gm1, eps = (R)g.eps;
+
+  // State of a (possibly ghost) point, fetched into registers ahead of its
+  // use; the boundary conditions (index map, reflection sign) are applied on
+  // use.
+  struct Pt {
+    double v[4];
+    bool fx, fy;
+  };
+  // A tile whose ghost layers all lie inside the grid needs no index map.
+  const bool interior = i0 >= NG && i0 + TX + NG <= g.nx && (!HASY || (j0 >= NG && j0 + TY + NG <= g.ny));
+  auto fetch_point = [&](int I, int J, Pt& p) {
+    size_t q;
+    if (interior) {
+      p.fx = false;
+      p.fy = false;
+      q = (size_t)J * g.nx + I;
+    } else {
+      p.fy = false;
+      const int si = map_index(I, g.nx, g.bc[0], g.bc[1], p.fx);
+      const int sj = HASY ? map_index(J, g.ny, g.bc[2], g.bc[3], p.fy) : 0;
+      q = (size_t)sj * g.nx + si;
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) p.v[c] = a.V[c * n + q];
+  };
+  auto point_state = [&](const Pt& p, R U[4]) {
+    U[0] = (R)p.v[0];
+    U[1] = (R)(p.fx ? -p.v[1] : p.v[1]);
+    U[2] = (R)(p.fy ? -p.v[2] : p.v[2]);
+    U[3] = (R)p.v[3];
+  };
+
+  // The x sweep's points and the control block are requested together, before
+  // anything waits for either: their latencies overlap.
+  constexpr int KPX = (NPX + NT - 1) / NT;
+  Pt px[KPX];
+#pragma unroll
+  for (int kk = 0; kk < KPX; ++kk) {
+    const int k = tid + kk * NT;
+    if (k < NPX) {
+      const int j = k / TXP, lx = k - j * TXP;
+      fetch_point(i0 + lx - NG, j0 + j, px[kk]);
+    }
+  }
+  const bool device_dt = !a.rhs_only && a.dt_mode == 1;
+  double t_prev = 0.0, dt_prev = 0.0;
+  int active_prev = 1;
+  if (device_dt) {
+    t_prev = ctl->t;
+    dt_prev = ctl->dt;
+    active_prev = ctl->active;
+  }
+
   // ---- speeds of this stage's input (LF alphas; CFL speed for stage 0)
   __shared__ double sSlot[3];
   double sp[3] = {a.fax, a.fay, 0.0};
@@ -335,23 +405,27 @@ __global__ __launch_bounds__(NTH) void stage_kernel(StageArgs a) {
   // ---- time step and whether this step is taken
   double dt = a.dt_host;
   bool active = true;
-  if (!a.rhs_only && a.dt_mode == 1) {
+  if (device_dt) {
     if (a.stage == 0) {
-      double t = ctl->t;
-      active = !(a.t_end > 0.0) || (t < a.t_end);
+      active = !(a.t_end > 0.0) || (t_prev < a.t_end);
       dt = cr_div(g.cfl_dmin, sp[2]);
-      if (a.t_end > 0.0 && t + dt > a.t_end) dt = a.t_end - t;
+      if (a.t_end > 0.0 && t_prev + dt > a.t_end) dt = a.t_end - t_prev;
       if (lead) {
         ctl->active = active ? 1 : 0;
         ctl->dt = dt;
         if (active && a.dt_rec) *a.dt_rec = dt;
       }
     } else {
-      dt = ctl->dt;
-      active = ctl->active != 0;
+      dt = dt_prev;
+      active = active_prev != 0;
     }
   }
   if (!active) return;
+  // In a launch whose workgroups are all resident at once, issue priority
+  // falls as a workgroup advances (3: x sweep, 2: y sweep, 1: per-cell
+  // phase), so the workgroups sharing a compute unit progress together
+  // instead of the last one running its latency-bound tail alone.
+  if (a.prio) __builtin_amdgcn_s_setprio(3);
 
   const double ax = a.frozen || a.rhs_only ? a.fax : sp[0];
   const double ay = a.frozen || a.rhs_only ? a.fay : sp[1];
@@ -369,33 +443,12 @@ __global__ __launch_bounds__(NTH) void stage_kernel(StageArgs a) {
       a.alpha_rec[3 + s] = ay;
     }
     if (s == 2 && a.dt_mode == 1) {
-      ctl->t = ctl->t + dt;
+      ctl->t = t_prev + dt;
       ctl->steps = ctl->steps + 1;
     }
   }
 
-  const int ntx = (g.nx + TX - 1) / TX;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int i0 = (tile % ntx) * TX;
-  const int j0 = (tile / ntx) * TY;
-  const size_t n = (size_t)g.nx * g.ny;
-  const R gamma = (R)g.gamma, gm1 = (R)g.gm1, eps = (R)g.eps;
-
-  // State of a (possibly ghost) point: boundary conditions applied on load.
-  auto load_point = [&](int I, int J, R U[4]) {
-    bool fx, fy = false;
-    const int si = map_index(I, g.nx, g.bc[0], g.bc[1], fx);
-    const int sj = HASY ? map_index(J, g.ny, g.bc[2], g.bc[3], fy) : 0;
-    const size_t q = (size_t)sj * g.nx + si;
-    const double r = a.V[q], mx = a.V[n + q], my = a.V[2 * n + q], E = a.V[3 * n + q];
-    U[0] = (R)r;
-    U[1] = (R)(fx ? -mx : mx);
-    U[2] = (R)(fy ? -my : my);
-    U[3] = (R)E;
-  };
-
   const int tx = tid % TX, ty = tid / TX;
-  const bool owner = tid < NCELL;
   R D[4] = {R(0), R(0), R(0), R(0)};
 
   // ---- 1. x sweep: split fluxes of the tile rows and their x-halo points
@@ -405,10 +458,12 @@ __global__ __launch_bounds__(NTH) void stage_kernel(StageArgs a) {
   // stencil read is done, then written over the split fluxes.
   {
     const R al = (R)ax;
-    for (int k = tid; k < NPX; k += NT) {
-      const int j = k / TXP, lx = k - j * TXP;
+#pragma unroll
+    for (int kk = 0; kk < KPX; ++kk) {
+      const int k = tid + kk * NT;
+      if (k >= NPX) break;
       R U[4];
-      load_point(i0 + lx - NG, j0 + j, U);
+      point_state(px[kk], U);
       R fp[4], fm[4];
       split_flux<0>(U, gamma, gm1, al, fp, fm);
 #pragma unroll
@@ -437,34 +492,28 @@ __global__ __launch_bounds__(NTH) void stage_kernel(StageArgs a) {
         for (int c = 0; c < 4; ++c) sFh[c * NFX + tid * (TX + 1) + TX] = fe[c];
       }
     } else {
-      // one (face, component) per work item
-      constexpr int KX = (4 * NFX + NT - 1) / NT;
-      R fh[KX];
+      // one (face, component) per work item: face tx of row ty for each
+      // component, then the last face of every row (f = TX) for the first 4 TY
+      // work items
+      R fh[4], fe = R(0);
+      const int base = ty * TXP + tx;
 #pragma unroll
-      for (int kk = 0; kk < KX; ++kk) {
-        const int t = tid + kk * NT;  // t = (c * TY + j) * (TX + 1) + f
-        if (t < 4 * NFX) {
-          const int f = t % (TX + 1);
-          const int rest = t / (TX + 1);
-          const int j = rest % TY, c = rest / TY;
-          const R* P = &sF[c][j * TXP + f];
-          const R* M = &sF[4 + c][j * TXP + f];
-          if constexpr (sizeof(R) == 8)
-            fh[kk] = weno5_face(P[0], P[1], P[2], P[3], P[4], M[5], M[4], M[3], M[2], M[1], eps);
-          else
-            fh[kk] = weno5(P[0], P[1], P[2], P[3], P[4], eps) + weno5(M[5], M[4], M[3], M[2], M[1], eps);
-        }
+      for (int c = 0; c < 4; ++c) {
+        fh[c] = face_value(&sF[c][base], &sF[4 + c][base], 1, eps);
+        asm volatile("" : "+v"(fh[c]) : : "memory");  // one component at a time: few live registers
       }
+      const bool extra = tid < 4 * TY;
+      const int ec = tid / TY, ej = tid - ec * TY;
+      if (extra) fe = face_value(&sF[ec][ej * TXP + TX], &sF[4 + ec][ej * TXP + TX], 1, eps);
       __syncthreads();
 #pragma unroll
-      for (int kk = 0; kk < KX; ++kk) {
-        const int t = tid + kk * NT;
-        if (t < 4 * NFX) sFh[t] = fh[kk];
-      }
+      for (int c = 0; c < 4; ++c) sFh[c * NFX + ty * (TX + 1) + tx] = fh[c];
+      if (extra) sFh[ec * NFX + ej * (TX + 1) + TX] = fe;
     }
     __syncthreads();
+    if (a.prio) __builtin_amdgcn_s_setprio(2);
     const R idx = (R)g.idx;
-    if (owner) {
+    {
 #pragma unroll
       for (int c = 0; c < 4; ++c)
         D[c] = (sFh[c * NFX + ty * (TX + 1) + tx + 1] - sFh[c * NFX + ty * (TX + 1) + tx]) * idx;
@@ -478,8 +527,10 @@ __global__ __launch_bounds__(NTH) void stage_kernel(StageArgs a) {
     const R al = (R)ay;
     for (int k = tid; k < NPY; k += NT) {
       const int ly = k / TX, i = k - ly * TX;
+      Pt pt;
+      fetch_point(i0 + i, j0 + ly - GY, pt);
       R U[4];
-      load_point(i0 + i, j0 + ly - GY, U);
+      point_state(pt, U);
       R fp[4], fm[4];
       split_flux<1>(U, gamma, gm1, al, fp, fm);
 #pragma unroll
@@ -507,35 +558,27 @@ __global__ __launch_bounds__(NTH) void stage_kernel(StageArgs a) {
         for (int c = 0; c < 4; ++c) sFh[c * NFY + TY * TX + tid] = fe[c];
       }
     } else {
-      constexpr int KY = HASY ? (4 * NFY + NT - 1) / NT : 1;
-      R fh[KY];
+      // face ty of column tx for each component, then the last face of every
+      // column (f = TY) for the first 4 TX work items
+      R fh[4], fe = R(0);
+      const int base = ty * TX + tx;
 #pragma unroll
-      for (int kk = 0; kk < KY; ++kk) {
-        const int t = tid + kk * NT;  // t = (c * (TY + 1) + f) * TX + i
-        if (t < 4 * NFY) {
-          const int i = t % TX;
-          const int rest = t / TX;
-          const int f = rest % (TY + 1), c = rest / (TY + 1);
-          const R* P = &sF[c][f * TX + i];
-          const R* M = &sF[4 + c][f * TX + i];
-          if constexpr (sizeof(R) == 8)
-            fh[kk] = weno5_face(P[0], P[TX], P[2 * TX], P[3 * TX], P[4 * TX], M[5 * TX], M[4 * TX],
-                                M[3 * TX], M[2 * TX], M[TX], eps);
-          else
-            fh[kk] = weno5(P[0], P[TX], P[2 * TX], P[3 * TX], P[4 * TX], eps) +
-                     weno5(M[5 * TX], M[4 * TX], M[3 * TX], M[2 * TX], M[TX], eps);
-        }
+      for (int c = 0; c < 4; ++c) {
+        fh[c] = face_value(&sF[c][base], &sF[4 + c][base], TX, eps);
+        asm volatile("" : "+v"(fh[c]) : : "memory");
       }
+      const bool extra = tid < 4 * TX;
+      const int ec = tid / TX, ei = tid - ec * TX;
+      if (extra) fe = face_value(&sF[ec][TY * TX + ei], &sF[4 + ec][TY * TX + ei], TX, eps);
       __syncthreads();
 #pragma unroll
-      for (int kk = 0; kk < KY; ++kk) {
-        const int t = tid + kk * NT;
-        if (t < 4 * NFY) sFh[t] = fh[kk];
-      }
+      for (int c = 0; c < 4; ++c) sFh[c * NFY + ty * TX + tx] = fh[c];
+      if (extra) sFh[ec * NFY + TY * TX + ei] = fe;
     }
     __syncthreads();
+    if (a.prio) __builtin_amdgcn_s_setprio(1);
     const R idy = (R)g.idy;
-    if (owner) {
+    {
 #pragma unroll
       for (int c = 0; c < 4; ++c)
         Dy[c] = (sFh[c * NFY + (ty + 1) * TX + tx] - sFh[c * NFY + ty * TX + tx]) * idy;
@@ -544,7 +587,7 @@ __global__ __launch_bounds__(NTH) void stage_kernel(StageArgs a) {
 
   // ---- 3. per cell: sources, L, stage combination, floors, check, maxima
   const int I = i0 + tx, J = j0 + ty;
-  const bool act = owner && I < g.nx && J < g.ny;
+  const bool act = I < g.nx && J < g.ny;
   double amax = 0.0, bmax = 0.0, smax = 0.0;
   bool bad = false;
   if (act) {
@@ -644,17 +687,41 @@ __global__ __launch_bounds__(NTH) void stage_kernel(StageArgs a) {
   }
 }
 
+// Whether nb workgroups of kernel k fit on the current device at once
+// (resident workgroups per compute unit x compute units), cached per device in
+// cap, which belongs to one kernel.
+template <typename K>
+bool one_round(K k, int threads, int nb, int* cap) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return false;
+  if (cap[dev] == 0) {
+    int per_cu = 0, ncu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, threads, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return false;
+    cap[dev] = per_cu * ncu > 0 ? per_cu * ncu : -1;
+  }
+  return nb <= cap[dev];
+}
+
 // Tile shapes: 16 x 16 cells (256 work items) in 2D; 256 x 1 in the 1D limit.
 template <typename R, bool CHAR>
 hipError_t launch_stage_variant(const StageArgs& a, hipStream_t s) {
+  StageArgs b = a;
   if (a.g.has_y) {
     constexpr int TX = 16, TY = 16;
+    static int cap[MAX_DEVICES];
+    const auto k = stage_kernel<R, TX, TY, true, CHAR>;
     const int nb = ((a.g.nx + TX - 1) / TX) * ((a.g.ny + TY - 1) / TY);
-    hipLaunchKernelGGL((stage_kernel<R, TX, TY, true, CHAR>), dim3(nb), dim3(TX * TY), 0, s, a);
+    b.prio = one_round(k, TX * TY, nb, cap) ? 1 : 0;
+    hipLaunchKernelGGL(k, dim3(nb), dim3(TX * TY), 0, s, b);
   } else {
     constexpr int TX = 256, TY = 1;
+    static int cap[MAX_DEVICES];
+    const auto k = stage_kernel<R, TX, TY, false, CHAR>;
     const int nb = (a.g.nx + TX - 1) / TX;
-    hipLaunchKernelGGL((stage_kernel<R, TX, TY, false, CHAR>), dim3(nb), dim3(TX * TY), 0, s, a);
+    b.prio = one_round(k, TX * TY, nb, cap) ? 1 : 0;
+    hipLaunchKernelGGL(k, dim3(nb), dim3(TX * TY), 0, s, b);
   }
   return hipGetLastError();
 }

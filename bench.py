@@ -59,9 +59,9 @@ POISSON_BYTES_PER_CELL_ITER = 8 * 4
 STAGE_TRAFFIC = {
     "sources": ["paper_1507_08549_amd/csrc/stage_kernel.hpp", "paper_1507_08549_amd/csrc/ieee.hpp",
                 "paper_1507_08549_amd/csrc/stage_fp64.hip", "paper_1507_08549_amd/csrc/hydro_internal.hpp"],
-    "sha256": "1c02f0f703ec9cf6dd6c1b9722c93fa3f4a6896efe183f58100de6d9c071ed49",
+    "sha256": "e6f64920e3c0d41aa6b1f7f4d1a51535b02d649580b4f3d96a24605f866d2be9",
     "n": 512,
-    "bytes_per_launch": (15.180 + 8.489) * 1e6,
+    "bytes_per_launch": (15.203 + 8.489) * 1e6,
 }
 
 
@@ -330,8 +330,8 @@ def levelset_leg(torch, hydro, inputs, n, steps, cpu):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=400)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--n", type=int, default=512, help="grid size (n x n)")
     ap.add_argument("--cpu-steps", type=int, default=40,
                     help="oracle steps timed for the CPU baseline (0: skip)")

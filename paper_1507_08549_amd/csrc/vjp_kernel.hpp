@@ -13,7 +13,8 @@
 //   * per face and component: nu * dW5/dv for both reconstructions (the
 //     derivative runs through the nonlinear weights: beta-adjoints
 //     -2 omega_k (q_k - W) / (eps + beta_k)), gathered at every point the
-//     stencils touch (a gather, so no atomics and a fixed summation order);
+//     stencils touch (by lane shifts within a wavefront: no atomics and a
+//     fixed summation order);
 //   * per point: dU += A(U)^T (phi+ + phi-) / 2 + alpha (phi+ - phi-) / 2 with
 //     A = dF/dU the flux Jacobian;
 //   * ghost points: their adjoint belongs to the cell they were copied from
@@ -22,9 +23,9 @@
 //     order: the x ghosts by the y pass at the x-edge cells, the y ghosts (and
 //     the x ghosts in the 1D limit) by a separate tiny kernel.
 // The x and y parts run as two passes (x: sources + x fluxes into a partial
-// sum; y: y fluxes, then the stage combination), each staging a tile with a
-// five-cell halo along its own axis in LDS and processing one component at a
-// time to bound the LDS footprint.
+// sum; y: y fluxes, then the stage combination), each taking grid lines along
+// its own axis, one wavefront per line and one point and face per lane, with
+// the line's split fluxes (six-point halo) staged in LDS.
 #pragma once
 
 #include "stage_kernel.hpp"
@@ -46,7 +47,12 @@ __device__ __forceinline__ void weno5_adj(const double v[5], double eps, double 
   const double w0 = s1 * s2, w1 = 6.0 * (s0 * s2), w2 = 3.0 * (s0 * s1);
   const double sw = w0 + w1 + w2;
   const double P = E0 * E1 * E2;
-  const double inv = 1.0 / (P * sw);
+  // 1 / (P sw): hardware reciprocal and two Newton steps (the adjoint needs
+  // no correctly rounded quotient; P sw is a normal positive number)
+  const double x = P * sw;
+  double inv = __builtin_amdgcn_rcp(x);
+  inv = __builtin_fma(inv, __builtin_fma(-x, inv, 1.0), inv);
+  inv = __builtin_fma(inv, __builtin_fma(-x, inv, 1.0), inv);
   const double isw = P * inv, iP = sw * inv;
   const double om0 = w0 * isw, om1 = w1 * isw, om2 = w2 * isw;
   const double q0 = (2.0 * v[0] - 7.0 * v[1] + 11.0 * v[2]) * (1.0 / 6.0);
@@ -150,27 +156,52 @@ struct VjpPass {
   const double* ghost_x;  // y pass: the x pass's ghost adjoints, merged at the x-edge cells
 };
 
-// One pass (DIR 0: x, with the source adjoint; DIR 1: y) over a tile of NA
-// cells along the axis and NC lines across it.
-template <typename R, int DIR, int NA, int NC>
-__global__ __launch_bounds__(256) void vjp_pass_kernel(VjpPass P) {
-  constexpr int NT = 256;
-  constexpr int LP = NA + 10;  // points with a five-cell halo
-  constexpr int LM = NA + 6;   // adjoint values with a three-cell halo
-  constexpr int LF = NA + 5;   // faces a0-2 .. a0+NA+2
-  static_assert(NA * NC <= NT && LF * NC == NT, "one face per work item, at most one tile cell");
-  // The state tile is only read before the component loop; the per-face
-  // derivative products are only written inside it: they share storage.
-  constexpr int NBUF = (4 * LP > 10 * LF ? 4 * LP : 10 * LF) * NC;
-  __shared__ R sBuf[NBUF];
-  __shared__ R sF[8][NC][LP];
-  __shared__ R sM[4][NC][LM];
-  R(*sU)[NC][LP] = reinterpret_cast<R(*)[NC][LP]>(sBuf);
-  R(*sD)[NC][LF] = reinterpret_cast<R(*)[NC][LF]>(sBuf);
+// Wavefront-wide lane shift (DPP wave_shr:1 / wave_shl:1): lane l receives
+// lane l - 1 (UP) or lane l + 1 (!UP) of x; a lane with no source receives 0.
+template <bool UP>
+__device__ __forceinline__ int lane_shift_bits(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, UP ? 0x138 : 0x130, 0xF, 0xF, true);
+}
+template <bool UP>
+__device__ __forceinline__ float lane_shift(float x) {
+  return __int_as_float(lane_shift_bits<UP>(__float_as_int(x)));
+}
+template <bool UP>
+__device__ __forceinline__ double lane_shift(double x) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo = (unsigned)lane_shift_bits<UP>((int)(unsigned)b);
+  const unsigned hi = (unsigned)lane_shift_bits<UP>((int)(unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// One pass (DIR 0: x, with the source adjoint; DIR 1: y) over NL lines of
+// the grid along the pass axis, one wavefront per line.  Lane l of a line
+// owns point k = a0 - 3 + l (the tile's NA = 58 cells are lanes 3..60; lanes
+// 0..2 and 61..63 are the ghost points where the line meets the domain edge)
+// and face k (between cells k - 1 and k).  Each lane differentiates both
+// reconstructions of its face; the stencil derivatives are gathered at the
+// points by lane shifts inside the wavefront (phi+(k) takes the f+
+// derivatives of faces k - 1 .. k + 3, phi-(k) the f- derivatives of faces
+// k - 2 .. k + 2), so the component loop has no barrier and no LDS writes.
+// The split fluxes of the line's points a0 - 6 .. a0 + 62 are staged in LDS
+// (each face reads five of each sign).  The x pass reads its own point's
+// state and adjoint straight from HBM (lanes run along rows); the y pass,
+// whose lanes run down columns, stages them through LDS with row-major
+// loads and transposes its results back to rows before the final writes.
+template <typename R, int DIR, int NL, bool STAGE_OWN>
+__global__ __launch_bounds__(64 * NL) void vjp_line_kernel(VjpPass P) {
+  constexpr int NT = 64 * NL;
+  constexpr int NA = 58;       // cells per line and tile
+  constexpr int LP = 69;       // staged points a0 - 6 .. a0 + 62
+  __shared__ R sF[8][NL][LP];
+  // (rows padded to 65 so that work items on neighbouring lines hit different banks)
+  __shared__ R sU[STAGE_OWN ? 4 : 1][NL][65];
+  __shared__ R sM[STAGE_OWN ? 4 : 1][NL][65];
 
   const VjpArgs& a = P.a;
   const Geom& g = a.g;
   const int tid = threadIdx.x;
+  const int wv = tid >> 6, L = tid & 63;
   const int na = DIR == 0 ? g.nx : g.ny;  // cells along the pass axis
   const int nc = DIR == 0 ? g.ny : g.nx;  // lines across it
   const int bc_lo = DIR == 0 ? g.bc[0] : g.bc[2];
@@ -178,7 +209,7 @@ __global__ __launch_bounds__(256) void vjp_pass_kernel(VjpPass P) {
   const int cn = DIR == 0 ? 1 : 2;
   const int nta = (na + NA - 1) / NA;
   const int a0 = (blockIdx.x % nta) * NA;
-  const int b0 = (blockIdx.x / nta) * NC;
+  const int b0 = (blockIdx.x / nta) * NL;
   const size_t n = (size_t)g.nx * g.ny;
   const R gamma = (R)g.gamma, gm1 = (R)g.gm1, eps = (R)g.eps;
   const R alpha = (R)(DIR == 0 ? a.ax : a.ay);
@@ -187,196 +218,184 @@ __global__ __launch_bounds__(256) void vjp_pass_kernel(VjpPass P) {
   auto gidx = [&](int along, int across) -> size_t {
     return DIR == 0 ? (size_t)across * g.nx + along : (size_t)along * g.nx + across;
   };
-
-  // ---- stage V (with ghosts along the axis) and mu (zero outside the domain)
-  for (int k = tid; k < NC * LP; k += NT) {
-    const int b = DIR == 0 ? k / LP : k % NC;
-    const int la = DIR == 0 ? k % LP : k / NC;
-    const int B = b0 + b < nc ? b0 + b : nc - 1;
+  // state of point k of line b (boundary conditions applied)
+  auto load_state = [&](int k, int b, R u4[4]) {
     bool flip;
-    const int s = map_index(a0 - 5 + la, na, bc_lo, bc_hi, flip);
-    const size_t q = gidx(s, B);
-    R u4[4];
+    const int s = map_index(k, na, bc_lo, bc_hi, flip);
+    const size_t q = gidx(s, b < nc ? b : nc - 1);
 #pragma unroll
     for (int c = 0; c < 4; ++c) u4[c] = (R)a.V[c * n + q];
     if (flip) u4[cn] = -u4[cn];
+  };
+  // adjoint of the cells (zero outside the domain)
+  auto load_mu = [&](int k, int b, R m4[4]) {
+    const bool in = k >= 0 && k < na && b < nc;
+    const size_t q = in ? gidx(k, b) : 0;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) sU[c][b][la] = u4[c];
+    for (int c = 0; c < 4; ++c) m4[c] = in ? (R)a.lam[c * n + q] : R(0);
+  };
+
+  // ---- stage the split fluxes (and, for the y pass, the own points' state
+  // and adjoint); consecutive work items take consecutive cells of a row
+  for (int t = tid; t < NL * LP; t += NT) {
+    const int b = DIR == 0 ? t / LP : t % NL;
+    const int p = DIR == 0 ? t % LP : t / NL;
+    R u4[4];
+    load_state(a0 - 6 + p, b0 + b, u4);
     R fp[4], fm[4];
     split_flux<DIR>(u4, gamma, gm1, alpha, fp, fm);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      sF[c][b][la] = fp[c];
-      sF[4 + c][b][la] = fm[c];
+      sF[c][b][p] = fp[c];
+      sF[4 + c][b][p] = fm[c];
+    }
+    if constexpr (STAGE_OWN) {
+      if (p >= 3 && p < 67) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sU[c][b][p - 3] = u4[c];
+      }
     }
   }
-  for (int k = tid; k < NC * LM; k += NT) {
-    const int b = DIR == 0 ? k / LM : k % NC;
-    const int lm = DIR == 0 ? k % LM : k / NC;
-    const int A = a0 - 3 + lm;
-    const bool in = A >= 0 && A < na && b0 + b < nc;
-    const size_t q = in ? gidx(A, b0 + b) : 0;
+  if constexpr (STAGE_OWN) {
+    for (int t = tid; t < NL * 64; t += NT) {
+      const int b = t % NL, l = t / NL;
+      R m4[4];
+      load_mu(a0 - 3 + l, b0 + b, m4);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) sM[c][b][lm] = in ? (R)a.lam[c * n + q] : R(0);
+      for (int c = 0; c < 4; ++c) sM[c][b][l] = m4[c];
+    }
+  }
+  const int k = a0 - 3 + L;  // this lane's point and face
+  const int line = b0 + wv;
+  R cu[4], mu[4];
+  if constexpr (!STAGE_OWN) {
+    load_state(k, line, cu);
+    load_mu(k, line, mu);
   }
   __syncthreads();
-
-  // ---- the points this work item owns: at most one tile cell, and possibly a ghost
-  const bool has_cell = tid < NA * NC;
-  const int pb0 = has_cell ? tid / NA : 0, pa0 = has_cell ? tid % NA : 0;
-  const bool own_lo = a0 == 0;
-  const bool own_hi = a0 <= na - 1 && na - 1 < a0 + NA;
-  const int ng = (own_lo ? 3 * NC : 0) + (own_hi ? 3 * NC : 0);
-  int gk = -1000, gb = 0;  // ghost point along index and line
-  if (tid < ng) {
-    int t = tid;
-    if (own_lo && t < 3 * NC) {
-      gb = t / 3;
-      gk = -1 - (t % 3);
-    } else {
-      if (own_lo) t -= 3 * NC;
-      gb = t / 3;
-      gk = na + (t % 3);
+  if constexpr (STAGE_OWN) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      cu[c] = sU[c][wv][L];
+      mu[c] = sM[c][wv][L];
     }
   }
-  const bool cell_act = has_cell && a0 + pa0 < na && b0 + pb0 < nc;
-  const bool ghost_act = tid < ng && b0 + gb < nc;
+
+  const bool line_ok = line < nc;
+  const bool face_in = L > 0 && k >= 0 && k <= na && line_ok;
+  const bool is_cell = L >= 3 && L < 3 + NA && k < na && line_ok;
+  const bool own_lo = a0 == 0, own_hi = a0 <= na - 1 && na - 1 < a0 + NA;
+  const bool is_ghost = line_ok && ((own_lo && k < 0) || (own_hi && k >= na && k < na + NG));
+  const JacPt<R> jc = jac_point<R>(cu[0], cu[1], cu[2], cu[3], gamma, gm1);
   R dU[4] = {R(0), R(0), R(0), R(0)};
-  R dG[4] = {R(0), R(0), R(0), R(0)};
-  R cu[4];  // the cell's own state (for the source terms)
-  JacPt<R> jc, jg;
-  {
-    const int la = pa0 + 5;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) cu[c] = sU[c][pb0][la];
-    jc = jac_point<R>(cu[0], cu[1], cu[2], cu[3], gamma, gm1);
-    const int lg = ghost_act ? gk - a0 + 5 : 5;
-    const int bb = ghost_act ? gb : 0;
-    jg = jac_point<R>(sU[0][bb][lg], sU[1][bb][lg], sU[2][bb][lg], sU[3][bb][lg], gamma, gm1);
-  }
-  __syncthreads();  // sU is dead from here; its storage holds sD
 
+#pragma unroll
   for (int c = 0; c < 4; ++c) {
-    // per face: nu * dW/dv of both reconstructions of component c
-    {
-      const int b = tid / LF, lf = tid % LF;
-      const int f = a0 - 2 + lf;  // global face index (face f: between cells f-1 and f)
-      const bool face_in = f >= 0 && f <= na && b0 + b < nc;
-      // local mu index of cell f is f - (a0 - 3) = lf + 1
-      const R nu = face_in ? (sM[c][b][lf + 1] - sM[c][b][lf]) * id : R(0);
-      R vp[5], vm[5], gp[5], gm[5];
+    // adjoint of the face value: (mu(k) - mu(k - 1)) / dx
+    const R mleft = lane_shift<true>(mu[c]);
+    const R nu = face_in ? (mu[c] - mleft) * id : R(0);
+    R vp[5], vm[5], gp[5], gm[5];
 #pragma unroll
-      for (int m = 0; m < 5; ++m) {
-        vp[m] = sF[c][b][lf + m];
-        vm[m] = sF[4 + c][b][lf + 5 - m];
-      }
-      weno5_adj(vp, eps, nu, gp);
-      weno5_adj(vm, eps, nu, gm);
+    for (int m = 0; m < 5; ++m) vp[m] = sF[c][wv][L + m];
+    weno5_adj(vp, eps, nu, gp);
+    // phi+(l) = gp0(l+3) + gp1(l+2) + gp2(l+1) + gp3(l) + gp4(l-1)
+    R t = gp[0];
+    t = lane_shift<false>(t) + gp[1];
+    t = lane_shift<false>(t) + gp[2];
+    t = lane_shift<false>(t) + gp[3];
+    R php = t + lane_shift<true>(gp[4]);
+    asm volatile("" : "+v"(php) : : "memory");  // the two signs one after the other
 #pragma unroll
-      for (int m = 0; m < 5; ++m) {
-        sD[m][b][lf] = gp[m];
-        sD[5 + m][b][lf] = gm[m];
-      }
-    }
-    __syncthreads();
-    // gather at the owned points: phi+(k) = sum_m D+_m(f = k+3-m), phi-(k) = sum_m D-_m(f = k-2+m)
-    auto gather = [&](int k, int b, R& php, R& phm) {
-      php = R(0);
-      phm = R(0);
-#pragma unroll
-      for (int m = 0; m < 5; ++m) {
-        const int lf1 = k + 3 - m - (a0 - 2);
-        if (lf1 >= 0 && lf1 < LF) php += sD[m][b][lf1];
-        const int lf2 = k - 2 + m - (a0 - 2);
-        if (lf2 >= 0 && lf2 < LF) phm += sD[5 + m][b][lf2];
-      }
-    };
-    {
-      R php, phm;
-      if (has_cell) {
-        gather(a0 + pa0, pb0, php, phm);
-        jacT_row<DIR, R>(c, jc, gamma, gm1, alpha, php + phm, php - phm, dU);
-      }
-      if (ghost_act) {
-        gather(gk, gb, php, phm);
-        jacT_row<DIR, R>(c, jg, gamma, gm1, alpha, php + phm, php - phm, dG);
-      }
-    }
-    __syncthreads();
+    for (int m = 0; m < 5; ++m) vm[m] = sF[4 + c][wv][L + 5 - m];
+    weno5_adj(vm, eps, nu, gm);
+    // phi-(l) = gm0(l-2) + gm1(l-1) + gm2(l) + gm3(l+1) + gm4(l+2)
+    R u = gm[0];
+    u = lane_shift<true>(u) + gm[1];
+    u = lane_shift<true>(u) + gm[2];
+    R w = gm[4];
+    w = lane_shift<false>(w) + gm[3];
+    const R phm = u + lane_shift<false>(w);
+    jacT_row<DIR, R>(c, jc, gamma, gm1, alpha, php + phm, php - phm, dU);
+    // one component at a time (few live registers)
+    asm volatile("" : "+v"(dU[0]), "+v"(dU[1]), "+v"(dU[2]), "+v"(dU[3]) : : "memory");
   }
 
   // ---- ghost adjoints to the side buffer (folded onto their source cells later)
-  if (ghost_act) {
-    const int side = gk < 0 ? 0 : 1;
-    const int layer = gk < 0 ? -gk - 1 : gk - na;
+  if (is_ghost) {
+    const int side = k < 0 ? 0 : 1;
+    const int layer = k < 0 ? -k - 1 : k - na;
 #pragma unroll
     for (int c = 0; c < 4; ++c)
-      P.ghost[(((size_t)side * 3 + layer) * nc + (b0 + gb)) * 4 + c] = (double)dG[c];
+      P.ghost[(((size_t)side * 3 + layer) * nc + line) * 4 + c] = (double)dU[c];
   }
-  // The y pass finalises with the cell index across the axis (x) fastest, so
-  // its global reads and writes are row segments: transpose dU through LDS.
-  int ca = pa0, cb = pb0;
-  bool cact = cell_act;
-  if (DIR == 1) {
-    R(*sT)[NC][NA] = reinterpret_cast<R(*)[NC][NA]>(sBuf);
-    if (has_cell)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) sT[c][pb0][pa0] = dU[c];
-    __syncthreads();
-    cb = tid % NC;
-    ca = tid / NC;
-    cact = has_cell && a0 + ca < na && b0 + cb < nc;
-    if (has_cell)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) dU[c] = sT[c][cb][ca];
-  }
-  if (!cact) return;
 
-  const size_t q = gidx(a0 + ca, b0 + cb);
+  // ---- per cell: sources (x pass), then the partial sum or the stage combination
+  int ca = k, cb = line;
+  bool cact = is_cell;
   double G[4];
   if (DIR == 0) {
-    // sources of Eq. euler2D, transposed
-    const R r = cu[0], E = cu[3];
-    const R m0 = sM[0][pb0][pa0 + 3], m1 = sM[1][pb0][pa0 + 3], m2 = sM[2][pb0][pa0 + 3],
-            m3 = sM[3][pb0][pa0 + 3];
-    const R gxv = g.grav ? (R)g.grav[q] : (R)g.gx;
-    const R gyv = g.grav ? (R)g.grav[n + q] : (R)g.gy;
-    R S[4];
-    S[0] = gxv * m1 + gyv * m2;
-    S[1] = gxv * m3;
-    S[2] = gyv * m3;
-    S[3] = R(0);
-    if (g.cyl) {
-      const double ri = g.xlo + ((double)(a0 + pa0) + 0.5) * g.dx;
-      const R ir = (R)(1.0 / ri);
-      const R u = jc.u, v = jc.v;
-      const R Eo = E / r;  // E / rho
-      // d/dU of (m_r, m_r u, m_z u, (E + p) u), transposed onto mu, times -1/r
-      S[0] -= ir * (-u * u * m1 - u * v * m2 + u * (R(2) * jc.hq - gamma * Eo) * m3);
-      S[1] -= ir * (m0 + R(2) * u * m1 + v * m2 + (gamma * Eo - jc.hq - gm1 * u * u) * m3);
-      S[2] -= ir * (u * m2 - gm1 * u * v * m3);
-      S[3] -= ir * (gamma * u * m3);
+    if (is_cell) {
+      const size_t q = gidx(k, line);
+      const R r = cu[0], E = cu[3];
+      const R m0 = mu[0], m1 = mu[1], m2 = mu[2], m3 = mu[3];
+      const R gxv = g.grav ? (R)g.grav[q] : (R)g.gx;
+      const R gyv = g.grav ? (R)g.grav[n + q] : (R)g.gy;
+      R S[4];
+      S[0] = gxv * m1 + gyv * m2;
+      S[1] = gxv * m3;
+      S[2] = gyv * m3;
+      S[3] = R(0);
+      if (g.cyl) {
+        const double ri = g.xlo + ((double)k + 0.5) * g.dx;
+        const R ir = (R)(1.0 / ri);
+        const R uu = jc.u, vv = jc.v;
+        const R Eo = E / r;  // E / rho
+        // d/dU of (m_r, m_r u, m_z u, (E + p) u), transposed onto mu, times -1/r
+        S[0] -= ir * (-uu * uu * m1 - uu * vv * m2 + uu * (R(2) * jc.hq - gamma * Eo) * m3);
+        S[1] -= ir * (m0 + R(2) * uu * m1 + vv * m2 + (gamma * Eo - jc.hq - gm1 * uu * uu) * m3);
+        S[2] -= ir * (uu * m2 - gm1 * uu * vv * m3);
+        S[3] -= ir * (gamma * uu * m3);
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) G[c] = (double)(S[c] + dU[c]);
     }
-#pragma unroll
-    for (int c = 0; c < 4; ++c) G[c] = (double)(S[c] + dU[c]);
   } else {
+    // lanes run down columns: transpose the cells' results through LDS so
+    // that the final reads and writes are row segments
+    R(*sT)[NA][NL + 1] = reinterpret_cast<R(*)[NA][NL + 1]>(&sF[0][0][0]);
+    static_assert(4 * NA * (NL + 1) <= 8 * NL * LP, "transpose fits in the split-flux storage");
+    __syncthreads();  // every wavefront is done with sF
+    if (L >= 3 && L < 3 + NA) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) G[c] = P.Gp[c * n + q] + (double)dU[c];
-    // x-ghost adjoints whose source is this cell (only cells within three of
-    // an x edge can be sources), in a fixed order
-    const int I = b0 + cb, J = a0 + ca;
-    if (I < NG || I >= g.nx - NG) {
-      for (int e = 0; e < 6; ++e) {
-        const int side = e / 3, layer = e % 3;
-        const int k = side == 0 ? -1 - layer : g.nx + layer;
-        bool flip;
-        if (map_index(k, g.nx, g.bc[0], g.bc[1], flip) != I) continue;
-        const double* gv = P.ghost_x + (((size_t)side * 3 + layer) * g.ny + J) * 4;
+      for (int c = 0; c < 4; ++c) sT[c][L - 3][wv] = dU[c];
+    }
+    __syncthreads();
+    cb = b0 + tid % NL;
+    const int la = tid / NL;
+    ca = a0 + la;
+    cact = la < NA && ca < na && cb < nc;
+    if (cact) {
+      const size_t q = gidx(ca, cb);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) G[c] += (flip && c == 1) ? -gv[c] : gv[c];
+      for (int c = 0; c < 4; ++c) G[c] = P.Gp[c * n + q] + (double)sT[c][la][tid % NL];
+      // x-ghost adjoints whose source is this cell (only cells within three
+      // of an x edge can be sources), in a fixed order
+      const int I = cb, J = ca;
+      if (I < NG || I >= g.nx - NG) {
+        for (int e = 0; e < 6; ++e) {
+          const int side = e / 3, layer = e % 3;
+          const int kk = side == 0 ? -1 - layer : g.nx + layer;
+          bool flip;
+          if (map_index(kk, g.nx, g.bc[0], g.bc[1], flip) != I) continue;
+          const double* gv = P.ghost_x + (((size_t)side * 3 + layer) * g.ny + J) * 4;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) G[c] += (flip && c == 1) ? -gv[c] : gv[c];
+        }
       }
     }
   }
+  if (!cact) return;
+  const size_t q = gidx(ca, cb);
   if (!P.finalize) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) P.Gp[c * n + q] = G[c];
@@ -384,7 +403,8 @@ __global__ __launch_bounds__(256) void vjp_pass_kernel(VjpPass P) {
   }
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    const double l = a.lam[c * n + q];
+    // the FP64 y pass has the cell's adjoint staged (lane layout: line, point)
+    const double l = STAGE_OWN && sizeof(R) == 8 ? (double)sM[c][cb - b0][ca - a0 + 3] : a.lam[c * n + q];
     double o = a.b * __builtin_fma(a.dt, G[c], l);
     if (a.acc) o += a.acc[c * n + q];
     if (a.side) {

@@ -13,17 +13,18 @@ hipError_t launch_vjp_impl(const VjpArgs& a, hipStream_t s) {
   double* gxb = a.ghost;
   double* gyb = a.ghost + a.ghost_y_offset;
   const int has_y = g.has_y;
+  constexpr int NA = 58, NL = 4;  // cells per line and tile, lines per workgroup
+  constexpr int NLY = 8;
+  constexpr bool SY = true;
   {
-    constexpr int NA = 59, NC = 4;
     VjpPass p{a, a.Gp, has_y ? 0 : 1, gxb, nullptr};
-    const int nb = ((g.nx + NA - 1) / NA) * ((g.ny + NC - 1) / NC);
-    hipLaunchKernelGGL((vjp_pass_kernel<R, 0, NA, NC>), dim3(nb), dim3(256), 0, s, p);
+    const int nb = ((g.nx + NA - 1) / NA) * ((g.ny + NL - 1) / NL);
+    hipLaunchKernelGGL((vjp_line_kernel<R, 0, NL, false>), dim3(nb), dim3(64 * NL), 0, s, p);
   }
   if (has_y) {
-    constexpr int NA = 27, NC = 8;
     VjpPass p{a, a.Gp, 1, gyb, gxb};
-    const int nb = ((g.ny + NA - 1) / NA) * ((g.nx + NC - 1) / NC);
-    hipLaunchKernelGGL((vjp_pass_kernel<R, 1, NA, NC>), dim3(nb), dim3(256), 0, s, p);
+    const int nb = ((g.ny + NA - 1) / NA) * ((g.nx + NLY - 1) / NLY);
+    hipLaunchKernelGGL((vjp_line_kernel<R, 1, NLY, SY>), dim3(nb), dim3(64 * NLY), 0, s, p);
   }
   const double scale = a.b * a.dt;
   if (!has_y)  // in 2D the y pass has merged the x ghosts

@@ -235,13 +235,10 @@ __global__ __launch_bounds__(64 * NL) void vjp_line_kernel(VjpPass P) {
     for (int c = 0; c < 4; ++c) m4[c] = in ? (R)a.lam[c * n + q] : R(0);
   };
 
-  // ---- stage the split fluxes (and, for the y pass, the own points' state
-  // and adjoint); consecutive work items take consecutive cells of a row
-  for (int t = tid; t < NL * LP; t += NT) {
-    const int b = DIR == 0 ? t / LP : t % NL;
-    const int p = DIR == 0 ? t % LP : t / NL;
-    R u4[4];
-    load_state(a0 - 6 + p, b0 + b, u4);
+  const int k = a0 - 3 + L;  // this lane's point and face
+  const int line = b0 + wv;
+  R cu[4], mu[4];
+  auto stage_point = [&](int p, int b, const R u4[4]) {
     R fp[4], fm[4];
     split_flux<DIR>(u4, gamma, gm1, alpha, fp, fm);
 #pragma unroll
@@ -249,14 +246,33 @@ __global__ __launch_bounds__(64 * NL) void vjp_line_kernel(VjpPass P) {
       sF[c][b][p] = fp[c];
       sF[4 + c][b][p] = fm[c];
     }
-    if constexpr (STAGE_OWN) {
+  };
+  if constexpr (!STAGE_OWN) {
+    // lanes run along rows: each wavefront stages its own line, lane l its own
+    // point (p = l + 3) and lanes 0..4 the five others (p = 0, 1, 2, 67, 68)
+    load_state(k, line, cu);
+    load_mu(k, line, mu);
+    stage_point(L + 3, wv, cu);
+    if (L < 5) {
+      const int p = L < 3 ? L : 64 + L;
+      R u4[4];
+      load_state(a0 - 6 + p, line, u4);
+      stage_point(p, wv, u4);
+    }
+  } else {
+    // lanes run down columns: stage the workgroup's points with row-major
+    // loads (consecutive work items take consecutive columns), the own
+    // points' state and adjoint with them
+    for (int t = tid; t < NL * LP; t += NT) {
+      const int b = t % NL, p = t / NL;
+      R u4[4];
+      load_state(a0 - 6 + p, b0 + b, u4);
+      stage_point(p, b, u4);
       if (p >= 3 && p < 67) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) sU[c][b][p - 3] = u4[c];
       }
     }
-  }
-  if constexpr (STAGE_OWN) {
     for (int t = tid; t < NL * 64; t += NT) {
       const int b = t % NL, l = t / NL;
       R m4[4];
@@ -264,13 +280,6 @@ __global__ __launch_bounds__(64 * NL) void vjp_line_kernel(VjpPass P) {
 #pragma unroll
       for (int c = 0; c < 4; ++c) sM[c][b][l] = m4[c];
     }
-  }
-  const int k = a0 - 3 + L;  // this lane's point and face
-  const int line = b0 + wv;
-  R cu[4], mu[4];
-  if constexpr (!STAGE_OWN) {
-    load_state(k, line, cu);
-    load_mu(k, line, mu);
   }
   __syncthreads();
   if constexpr (STAGE_OWN) {

@@ -200,17 +200,20 @@ int vjp_impl(hydro_ctx* c, const double* U_n, const double* R1, const double* R2
   v.ghost = c->ghost;
   v.ghost_y_offset = 2 * 3 * 4 * (size_t)(c->p.nx > c->p.ny ? c->p.nx : c->p.ny);
   v.Gp = c->X[4];
-  // stage 3 (input R2): lam2 = 2/3 (lam3 + dt J^T lam3);  lam_prev = 1/3 lam3
+  // stage 3 (input R2): lam2 = 2/3 (lam3 + dt J^T lam3)
   v.V = R2; v.lam = lam_next; v.b = kStageWeight[2]; v.ax = alpha->ax[2]; v.ay = alpha->ay[2];
-  v.out = lam2; v.acc = nullptr; v.side = lam_prev; v.side_in = nullptr;
+  v.out = lam2;
   HY_CHECK(hy::launch_stage_vjp(v, c->stream));
-  // stage 2 (input R1): lam1 = 1/4 (lam2 + dt J^T lam2);  lam_prev += 3/4 lam2
+  // stage 2 (input R1): lam1 = 1/4 (lam2 + dt J^T lam2)
   v.V = R1; v.lam = lam2; v.b = kStageWeight[1]; v.ax = alpha->ax[1]; v.ay = alpha->ay[1];
-  v.out = lam1; v.acc = nullptr; v.side = lam_prev; v.side_in = lam_prev;
+  v.out = lam1;
   HY_CHECK(hy::launch_stage_vjp(v, c->stream));
-  // stage 1 (input U_n = U0, b = 1): lam_prev += lam1 + dt J^T lam1
+  // stage 1 (input U_n = U0, b = 1), plus the U0 shares of stages 3 and 2:
+  // lam_prev = (lam1 + dt J^T lam1) + 1/3 lam3 + 3/4 lam2
   v.V = U_n; v.lam = lam1; v.b = kStageWeight[0]; v.ax = alpha->ax[0]; v.ay = alpha->ay[0];
-  v.out = lam_prev; v.acc = lam_prev; v.side = nullptr; v.side_in = nullptr;
+  v.out = lam_prev;
+  v.add0 = lam_next; v.c0 = 1.0 - kStageWeight[2];
+  v.add1 = lam2; v.c1 = 1.0 - kStageWeight[1];
   HY_CHECK(hy::launch_stage_vjp(v, c->stream));
   return HYDRO_OK;
 }

@@ -5,11 +5,13 @@
 
 namespace hy {
 
-// One Runge-Kutta stage W = U0 + b ((V - U0) + dt L(V)) transposed:
-//   out  = b (lam + dt J_L(V)^T lam) + (acc ? acc : 0)     (adjoint of V)
-//   side = (side_in ? side_in : 0) + (1 - b) lam            (adjoint of U0), if side
-// with the LF speeds (ax, ay) held fixed.  out may alias acc, side may alias
-// side_in; neither may alias lam or V.
+// One Runge-Kutta stage W = U0 + b ((V - U0) + dt L(V)) transposed, with the
+// LF speeds (ax, ay) held fixed:
+//   out = b (lam + dt J_L(V)^T lam) + c0 add0 + c1 add1     (adjoint of V)
+// (add0, add1 optional).  The adjoint of U0, (1 - b) lam, is not written:
+// the caller adds the stages' shares where the step's adjoint is formed
+// (through add0 / add1 of the first stage).  out may not alias lam, V, add0
+// or add1.
 struct VjpArgs {
   Geom g;
   double dt;
@@ -19,12 +21,13 @@ struct VjpArgs {
   double b;
   double ax, ay;
   double* out;
-  const double* acc;
-  double* side;
-  const double* side_in;
+  const double* add0;
+  double c0;
+  const double* add1;
+  double c1;
   double* ghost;  // scratch: adjoint of ghost cells, [2][3][ny][4] then [2][3][nx][4]
   size_t ghost_y_offset;  // offset (doubles) of the y part in ghost
-  double* Gp;     // scratch state: partial J_L^T lam between the x and y passes
+  void* Gp;       // scratch: partial J_L^T lam between the x and y passes, 4 n values of the pass precision
 };
 
 hipError_t launch_stage_vjp(const VjpArgs& a, hipStream_t s);

@@ -150,8 +150,8 @@ __device__ __forceinline__ void jacT_row(int c, const JacPt<R>& j, R gamma, R gm
 
 struct VjpPass {
   VjpArgs a;
-  double* Gp;      // partial J_L^T mu (x pass writes, y pass reads)
-  int finalize;    // this pass writes out / side
+  void* Gp;        // partial J_L^T mu in the pass precision (x pass writes, y pass reads)
+  int finalize;    // this pass writes out
   double* ghost;   // ghost adjoints of this pass's axis: [2][3][n_across][4]
   const double* ghost_x;  // y pass: the x pass's ghost adjoints, merged at the x-edge cells
 };
@@ -385,8 +385,9 @@ __global__ __launch_bounds__(64 * NL) void vjp_line_kernel(VjpPass P) {
     cact = la < NA && ca < na && cb < nc;
     if (cact) {
       const size_t q = gidx(ca, cb);
+      const R* gp = static_cast<const R*>(P.Gp);
 #pragma unroll
-      for (int c = 0; c < 4; ++c) G[c] = P.Gp[c * n + q] + (double)sT[c][la][tid % NL];
+      for (int c = 0; c < 4; ++c) G[c] = (double)gp[c * n + q] + (double)sT[c][la][tid % NL];
       // x-ghost adjoints whose source is this cell (only cells within three
       // of an x edge can be sources), in a fixed order
       const int I = cb, J = ca;
@@ -406,8 +407,10 @@ __global__ __launch_bounds__(64 * NL) void vjp_line_kernel(VjpPass P) {
   if (!cact) return;
   const size_t q = gidx(ca, cb);
   if (!P.finalize) {
+    // (the x pass's partial sum is a value of the pass precision: exact in it)
+    R* gp = static_cast<R*>(P.Gp);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) P.Gp[c * n + q] = G[c];
+    for (int c = 0; c < 4; ++c) gp[c * n + q] = (R)G[c];
     return;
   }
 #pragma unroll
@@ -415,11 +418,8 @@ __global__ __launch_bounds__(64 * NL) void vjp_line_kernel(VjpPass P) {
     // the FP64 y pass has the cell's adjoint staged (lane layout: line, point)
     const double l = STAGE_OWN && sizeof(R) == 8 ? (double)sM[c][cb - b0][ca - a0 + 3] : a.lam[c * n + q];
     double o = a.b * __builtin_fma(a.dt, G[c], l);
-    if (a.acc) o += a.acc[c * n + q];
-    if (a.side) {
-      const double s = (1.0 - a.b) * l;
-      a.side[c * n + q] = a.side_in ? a.side_in[c * n + q] + s : s;
-    }
+    if (a.add0) o += a.c0 * a.add0[c * n + q];
+    if (a.add1) o += a.c1 * a.add1[c * n + q];
     a.out[c * n + q] = o;
   }
 }

@@ -14,7 +14,7 @@ hipError_t launch_vjp_impl(const VjpArgs& a, hipStream_t s) {
   double* gyb = a.ghost + a.ghost_y_offset;
   const int has_y = g.has_y;
   constexpr int NA = 58, NL = 4;  // cells per line and tile, lines per workgroup
-  constexpr int NLY = 8;
+  constexpr int NLY = sizeof(R) == 4 ? 16 : 8;  // columns per y-pass workgroup (16: 128-byte rows of the FP64 state)
   constexpr bool SY = true;
   {
     VjpPass p{a, a.Gp, has_y ? 0 : 1, gxb, nullptr};

@@ -62,10 +62,17 @@ STAGE_TRAFFIC = {
     "sha256": "e6f64920e3c0d41aa6b1f7f4d1a51535b02d649580b4f3d96a24605f866d2be9",
     "n": 512,
     "bytes_per_launch": (15.203 + 8.489) * 1e6,
+    # SQ_INSTS_VALU of the same launch (wavefront instructions), same digest
+    "valu_insts_per_launch": 6755332,
 }
+# VALU issue peak: 256 CUs x 4 SIMDs, one wave64 instruction per 4 cycles per
+# SIMD at 2.4 GHz (FP64 add, mul and fma issue at that rate).
+PEAK_VALU_WAVE_INSTS_PER_S = 256 * 4 * 2.4e9 / 4
 
 
-def stage_traffic(n):
+def stage_measured(n, key):
+    """A counter figure of the stage kernel (HBM bytes or VALU instructions per
+    launch), or None once its sources or the grid differ from the measured."""
     import hashlib
     h = hashlib.sha256()
     for f in STAGE_TRAFFIC["sources"]:
@@ -73,7 +80,11 @@ def stage_traffic(n):
             h.update(fh.read())
     if h.hexdigest() != STAGE_TRAFFIC["sha256"] or n != STAGE_TRAFFIC["n"]:
         return None
-    return STAGE_TRAFFIC["bytes_per_launch"]
+    return STAGE_TRAFFIC[key]
+
+
+def stage_traffic(n):
+    return stage_measured(n, "bytes_per_launch")
 
 
 def log(*a):
@@ -385,6 +396,12 @@ def main():
     # stage-kernel average duration: 3 stage launches per step (plus three tiny
     # set-up kernels per call, included, so the estimate is conservative)
     stage_s = t64 / (3 * args.steps)
+    # the binding roof as instruction issue: measured VALU instructions per
+    # launch over the launch time, against the issue peak
+    insts = stage_measured(n, "valu_insts_per_launch")
+    issue = None if insts is None else {
+        "valu_wave_insts_per_launch": insts, "achieved_per_s": insts / stage_s,
+        "peak_per_s": PEAK_VALU_WAVE_INSTS_PER_S, "frac": insts / stage_s / PEAK_VALU_WAVE_INSTS_PER_S}
     flops_launch = FLOPS_PER_CELL_STAGE * ncell
     achieved_tf = flops_launch / stage_s / 1e12
     hbm_gbs = BYTES_PER_CELL_STEP * ncell / 3 / stage_s / 1e9
@@ -492,7 +509,7 @@ def main():
                      "algorithmic_bytes_per_launch": BYTES_PER_CELL_STEP * ncell / 3,
                      "kernel": "stage_kernel<double,16,16>",
                      "avg_launch_us": stage_s * 1e6, "hbm_gbs_algorithmic": hbm_gbs,
-                     "hbm_frac": hbm_gbs / PEAK_HBM_GBS},
+                     "hbm_frac": hbm_gbs / PEAK_HBM_GBS, "issue": issue},
         "cpu_baseline": cpu,
         "fp32_bulk": fp32,
         "adjoint": adj,

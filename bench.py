@@ -370,7 +370,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
+        print("bench.py: the solver runs on one GPU only; --gpus must be 1 "
               "(the multi-GPU decomposition is a design, not an implementation)", file=sys.stderr)
         sys.exit(2)
 

@@ -124,7 +124,7 @@ def test_gresho_error_table(torch, hydro):
         rows.append((abs(s1[0] - s0[0]) / s0[0], abs(s1[3] - s0[3]) / s0[3],
                      np.abs(p1 - p0).sum() / (n * n)))
     rows = np.array(rows)
-    print("\nGresho t = 3: n, dM/M, dE/E, L1(p) (this build | paper)")
+    print("\nGresho t = 3: n, dM/M, dE/E, L1(p) (SSP-RK3 here | paper)")
     for n, r, pr in zip((50, 100, 200, 400), rows, paper):
         print(f"{n:4d} {r[0]:.2e} {r[1]:.2e} {r[2]:.2e} | {pr[3]:.2e} {pr[4]:.2e} {pr[5]:.2e}")
     assert np.all(np.diff(rows[:, 2]) < 0), rows

@@ -9,8 +9,8 @@ Sizes: tiny grids for every boundary combination and both geometries
 (several tiles, ragged edges, grids smaller than one tile), then the full
 sizes of the workloads (shock tube 400 x 1; shear layer 512^2; heavy-over-
 light layer 256 x 1024; polytrope 1024^2 in (r, z) with a gravity field and
-the density floor; sine-mode shear layer 1024^2), a few steps each, whole
-grid compared.
+the density floor; sine-mode shear layer 1024^2; the shear layer at 4096^2),
+a few steps each, whole grid compared.
 """
 import numpy as np
 import pytest
@@ -187,6 +187,21 @@ def test_kh_sine_1024_bitwise(torch, hydro, oracle_mod):
     U = _dev(torch, U0)
     s.run(U, 1)
     _assert_same(U.cpu().numpy(), want, "sine-mode KH 1024^2, 1 step")
+
+
+def test_shear_layer_4096_one_step_bitwise(torch, hydro, oracle_mod):
+    """The largest grid the benchmark times (4096^2, 16.8M cells, 65536
+    tiles: many rounds of workgroups, states far beyond the last-level cache):
+    one step with the device time step, whole grid compared (the oracle needs
+    about ten seconds)."""
+    prm, U0 = inputs.kelvin_helmholtz(4096, seed=2)
+    o = oracle_mod.Oracle(prm)
+    want, t, _, _ = o.run(U0, 1)
+    s = hydro.Solver(prm)
+    U = _dev(torch, U0)
+    k, t_gpu, _, _ = s.run(U, 1)
+    assert k == 1 and t_gpu == t
+    _assert_same(U.cpu().numpy(), want, "shear layer 4096^2, 1 step")
 
 
 def test_kh_small_long_run_bitwise(torch, hydro, oracle_mod):

@@ -80,6 +80,22 @@ def test_step_vjp_matches_reference(torch, hydro, oracle_mod, shape, bc, geometr
     assert err <= 1e-11, err
 
 
+def test_step_vjp_full_size(torch, hydro, oracle_mod):
+    """The adjoint workload's grid (sine-mode shear layer, 1024^2: 18 tiles of
+    58 cells along every line, lines in many workgroups), one step, against
+    the reference adjoint (about ten seconds and 10 GB of host memory)."""
+    from oracle import torch_ref
+    prm = inputs.kh_sine_params(1024)
+    U0 = inputs.kh_sine_state(inputs.kh_sine_amplitudes(), prm)
+    o = oracle_mod.Oracle(prm)
+    dt = o.cfl(U0)
+    _, al = o.step(U0, dt)
+    lam = np.random.default_rng(3).standard_normal(U0.shape)
+    want = torch_ref.vjp(prm, None, U0, dt, al, lam)
+    got = hydro.Solver(prm).step_vjp(_dev(torch, U0), dt, al, _dev(torch, lam)).cpu().numpy()
+    assert _rel_l1(got, want) <= 1e-11
+
+
 @pytest.mark.parametrize("n", [7, 300], ids=lambda n: f"n{n}")
 def test_step_vjp_1d(torch, hydro, oracle_mod, n):
     from oracle import torch_ref

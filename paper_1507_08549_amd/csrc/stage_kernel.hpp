@@ -267,19 +267,41 @@ __device__ __forceinline__ R face_value(const R* P, const R* M, int st, R eps) {
            weno5(M[5 * st], M[4 * st], M[3 * st], M[2 * st], M[st], eps);
 }
 
+// Max of a non-negative x over the wavefront, valid in lane 63 (exact: a max
+// of doubles).  DPP row shifts by 1, 2, 4, 8 (a lane with no source reads 0)
+// leave each 16-lane row's max in its lane 15; row_bcast:15 and
+// row_bcast:31 then carry the row maxima up to the last row.  No LDS round
+// trips, unlike lane shuffles.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_move(double old, double x) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const unsigned long long o = (unsigned long long)__double_as_longlong(old);
+  const unsigned lo =
+      (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)o, (int)(unsigned)b, CTRL, ROWS, 0xF, true);
+  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)(o >> 32), (int)(unsigned)(b >> 32),
+                                                            CTRL, ROWS, 0xF, true);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ double wave_max_nonneg(double x) {
+  x = __builtin_fmax(x, dpp_move<0x111, 0xF>(0.0, x));  // row_shr:1
+  x = __builtin_fmax(x, dpp_move<0x112, 0xF>(0.0, x));  // row_shr:2
+  x = __builtin_fmax(x, dpp_move<0x114, 0xF>(0.0, x));  // row_shr:4
+  x = __builtin_fmax(x, dpp_move<0x118, 0xF>(0.0, x));  // row_shr:8
+  x = __builtin_fmax(x, dpp_move<0x142, 0xA>(x, x));    // row_bcast:15 into rows 1, 3
+  x = __builtin_fmax(x, dpp_move<0x143, 0xC>(x, x));    // row_bcast:31 into rows 2, 3
+  return x;
+}
+
 // Max over the NSUB sub-slots of ring slot s, by wavefront 0, broadcast to the
 // block through LDS.  Every work item of the block must call it.
 __device__ __forceinline__ void read_slot(const Ctl* ctl, int s, double out[3], double* sh) {
+  static_assert(NSUB == 64, "one sub-slot per lane of a wavefront");
   if (threadIdx.x < NSUB) {
     const unsigned long long* p = ctl->slot[s][threadIdx.x];
-    double m0 = as_double(p[0]), m1 = as_double(p[1]), m2 = as_double(p[2]);
-#pragma unroll
-    for (int off = NSUB / 2; off > 0; off >>= 1) {
-      m0 = __builtin_fmax(m0, __shfl_xor(m0, off));
-      m1 = __builtin_fmax(m1, __shfl_xor(m1, off));
-      m2 = __builtin_fmax(m2, __shfl_xor(m2, off));
-    }
-    if (threadIdx.x == 0) {
+    const double m0 = wave_max_nonneg(as_double(p[0]));
+    const double m1 = wave_max_nonneg(as_double(p[1]));
+    const double m2 = wave_max_nonneg(as_double(p[2]));
+    if (threadIdx.x == NSUB - 1) {
       sh[0] = m0;
       sh[1] = m1;
       sh[2] = m2;
@@ -658,22 +680,23 @@ __global__ __launch_bounds__(TX * TY) void stage_kernel(StageArgs a) {
     return;
   }
 
-  // ---- maxima: wavefront shuffles, then LDS across the workgroup's waves,
-  // then one atomic max per quantity (exact and order-free).
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    amax = __builtin_fmax(amax, __shfl_xor(amax, off));
-    bmax = __builtin_fmax(bmax, __shfl_xor(bmax, off));
-    smax = __builtin_fmax(smax, __shfl_xor(smax, off));
-  }
+  // ---- maxima: within each wavefront (DPP), then LDS across the
+  // workgroup's waves, then one atomic max per quantity (exact and
+  // order-free).
+  amax = wave_max_nonneg(amax);
+  bmax = wave_max_nonneg(bmax);
+  smax = wave_max_nonneg(smax);
   const int wave = tid / 64;
-  if ((tid & 63) == 0) {
+  if ((tid & 63) == 63) {
     sRed[wave][0] = amax;
     sRed[wave][1] = bmax;
     sRed[wave][2] = smax;
   }
   const int anybad = __syncthreads_or(bad ? 1 : 0);
   if (tid == 0) {
+    amax = sRed[0][0];
+    bmax = sRed[0][1];
+    smax = sRed[0][2];
     for (int k = 1; k < NW; ++k) {
       amax = __builtin_fmax(amax, sRed[k][0]);
       bmax = __builtin_fmax(bmax, sRed[k][1]);

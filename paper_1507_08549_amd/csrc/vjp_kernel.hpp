@@ -18,10 +18,12 @@
 //   * per point: dU += A(U)^T (phi+ + phi-) / 2 + alpha (phi+ - phi-) / 2 with
 //     A = dF/dU the flux Jacobian;
 //   * ghost points: their adjoint belongs to the cell they were copied from
-//     (periodic image, mirror with the normal momentum negated, or the edge
-//     cell); it is written to a small side buffer and folded back in a fixed
-//     order: the x ghosts by the y pass at the x-edge cells, the y ghosts (and
-//     the x ghosts in the 1D limit) by a separate tiny kernel.
+//     (mirror with the normal momentum negated, or the edge cell); it is
+//     written to a small side buffer and folded back in a fixed order: the x
+//     ghosts by the y pass at the x-edge cells, the y ghosts (and the x ghosts
+//     in the 1D limit) by a separate tiny kernel.  A periodic axis has no
+//     ghost points: its lines are rings (faces and stencils wrap), so every
+//     contribution lands on a cell directly.
 // The x and y parts run as two passes (x: sources + x fluxes into a partial
 // sum; y: y fluxes, then the stage combination), each taking grid lines along
 // its own axis, one wavefront per line and one point and face per lane, with
@@ -206,6 +208,10 @@ __global__ __launch_bounds__(64 * NL) void vjp_line_kernel(VjpPass P) {
   const int nc = DIR == 0 ? g.ny : g.nx;  // lines across it
   const int bc_lo = DIR == 0 ? g.bc[0] : g.bc[2];
   const int bc_hi = DIR == 0 ? g.bc[1] : g.bc[3];
+  // A periodic line is a ring: every point index is a cell (taken modulo the
+  // line length), the faces wrap, and there are no ghost points whose
+  // adjoints would need folding onto cells of another tile.
+  const bool ring = bc_lo == PERIODIC;
   const int cn = DIR == 0 ? 1 : 2;
   const int nta = (na + NA - 1) / NA;
   const int a0 = (blockIdx.x % nta) * NA;
@@ -218,19 +224,20 @@ __global__ __launch_bounds__(64 * NL) void vjp_line_kernel(VjpPass P) {
   auto gidx = [&](int along, int across) -> size_t {
     return DIR == 0 ? (size_t)across * g.nx + along : (size_t)along * g.nx + across;
   };
+  auto wrap = [&](int k) { return ((k % na) + na) % na; };
   // state of point k of line b (boundary conditions applied)
   auto load_state = [&](int k, int b, R u4[4]) {
-    bool flip;
-    const int s = map_index(k, na, bc_lo, bc_hi, flip);
+    bool flip = false;
+    const int s = ring ? wrap(k) : map_index(k, na, bc_lo, bc_hi, flip);
     const size_t q = gidx(s, b < nc ? b : nc - 1);
 #pragma unroll
     for (int c = 0; c < 4; ++c) u4[c] = (R)a.V[c * n + q];
     if (flip) u4[cn] = -u4[cn];
   };
-  // adjoint of the cells (zero outside the domain)
+  // adjoint of the cells (zero outside the domain; a ring has no outside)
   auto load_mu = [&](int k, int b, R m4[4]) {
-    const bool in = k >= 0 && k < na && b < nc;
-    const size_t q = in ? gidx(k, b) : 0;
+    const bool in = (ring || (k >= 0 && k < na)) && b < nc;
+    const size_t q = in ? gidx(ring ? wrap(k) : k, b) : 0;
 #pragma unroll
     for (int c = 0; c < 4; ++c) m4[c] = in ? (R)a.lam[c * n + q] : R(0);
   };
@@ -291,10 +298,10 @@ __global__ __launch_bounds__(64 * NL) void vjp_line_kernel(VjpPass P) {
   }
 
   const bool line_ok = line < nc;
-  const bool face_in = L > 0 && k >= 0 && k <= na && line_ok;
+  const bool face_in = L > 0 && (ring || (k >= 0 && k <= na)) && line_ok;
   const bool is_cell = L >= 3 && L < 3 + NA && k < na && line_ok;
   const bool own_lo = a0 == 0, own_hi = a0 <= na - 1 && na - 1 < a0 + NA;
-  const bool is_ghost = line_ok && ((own_lo && k < 0) || (own_hi && k >= na && k < na + NG));
+  const bool is_ghost = !ring && line_ok && ((own_lo && k < 0) || (own_hi && k >= na && k < na + NG));
   const JacPt<R> jc = jac_point<R>(cu[0], cu[1], cu[2], cu[3], gamma, gm1);
   R dU[4] = {R(0), R(0), R(0), R(0)};
 
@@ -391,7 +398,7 @@ __global__ __launch_bounds__(64 * NL) void vjp_line_kernel(VjpPass P) {
       // x-ghost adjoints whose source is this cell (only cells within three
       // of an x edge can be sources), in a fixed order
       const int I = cb, J = ca;
-      if (I < NG || I >= g.nx - NG) {
+      if (g.bc[0] != PERIODIC && (I < NG || I >= g.nx - NG)) {
         for (int e = 0; e < 6; ++e) {
           const int side = e / 3, layer = e % 3;
           const int kk = side == 0 ? -1 - layer : g.nx + layer;

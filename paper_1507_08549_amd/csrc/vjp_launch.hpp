@@ -26,11 +26,12 @@ hipError_t launch_vjp_impl(const VjpArgs& a, hipStream_t s) {
     const int nb = ((g.ny + NA - 1) / NA) * ((g.nx + NLY - 1) / NLY);
     hipLaunchKernelGGL((vjp_line_kernel<R, 1, NLY, SY>), dim3(nb), dim3(64 * NLY), 0, s, p);
   }
+  // (a periodic axis has no ghost adjoints to fold)
   const double scale = a.b * a.dt;
-  if (!has_y)  // in 2D the y pass has merged the x ghosts
+  if (!has_y && g.bc[0] != PERIODIC)  // in 2D the y pass has merged the x ghosts
     hipLaunchKernelGGL(vjp_fold_kernel<R>, dim3((4 * g.ny + 255) / 256), dim3(256), 0, s, g, 0,
                        (const double*)gxb, a.out, scale);
-  else
+  else if (has_y && g.bc[2] != PERIODIC)
     hipLaunchKernelGGL(vjp_fold_kernel<R>, dim3((4 * g.nx + 255) / 256), dim3(256), 0, s, g, 1,
                        (const double*)gyb, a.out, scale);
   return hipGetLastError();

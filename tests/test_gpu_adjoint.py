@@ -56,7 +56,8 @@ def _rel_l1(got, want):
 BCS = [[P, P, P, P], [T, T, T, T], [R, R, R, R], [R, T, R, T], [T, R, P, P]]
 # (116, 58): lines of exactly two and one 58-cell tiles (the ghost points of
 # the last tile's line are its last three lanes)
-SHAPES = [(8, 8), (11, 13), (17, 33), (40, 70), (70, 130), (116, 58)]
+# (3, 5): lines shorter than a stencil (periodic lines wrap more than once)
+SHAPES = [(3, 5), (8, 8), (11, 13), (17, 33), (40, 70), (70, 130), (116, 58)]
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: f"{s[0]}x{s[1]}")

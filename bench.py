@@ -59,11 +59,11 @@ POISSON_BYTES_PER_CELL_ITER = 8 * 4
 STAGE_TRAFFIC = {
     "sources": ["paper_1507_08549_amd/csrc/stage_kernel.hpp", "paper_1507_08549_amd/csrc/ieee.hpp",
                 "paper_1507_08549_amd/csrc/stage_fp64.hip", "paper_1507_08549_amd/csrc/hydro_internal.hpp"],
-    "sha256": "e6f64920e3c0d41aa6b1f7f4d1a51535b02d649580b4f3d96a24605f866d2be9",
+    "sha256": "b62b8d6324de5cf34f93a42f1284348b3d8488d52e53447d2beba5e6a9b84471",
     "n": 512,
-    "bytes_per_launch": (15.203 + 8.489) * 1e6,
+    "bytes_per_launch": (15.194 + 8.489) * 1e6,
     # SQ_INSTS_VALU of the same launch (wavefront instructions), same digest
-    "valu_insts_per_launch": 6755332,
+    "valu_insts_per_launch": 6804486,
 }
 # VALU issue peak: 256 CUs x 4 SIMDs, one wave64 instruction per 4 cycles per
 # SIMD at 2.4 GHz (FP64 add, mul and fma issue at that rate).

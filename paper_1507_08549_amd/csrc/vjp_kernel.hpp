@@ -19,13 +19,13 @@
 //     A = dF/dU the flux Jacobian;
 //   * ghost points: their adjoint belongs to the cell they were copied from
 //     (mirror with the normal momentum negated, or the edge cell); it is
-//     written to a small side buffer and folded back in a fixed order: the x
-//     ghosts by the y pass at the x-edge cells, the y ghosts (and the x ghosts
-//     in the 1D limit) by a separate tiny kernel.  A periodic axis has no
+//     written to a small side buffer and folded back in a fixed order: the y
+//     ghosts by the x pass at the y-edge cells, the x ghosts by a separate
+//     tiny kernel.  A periodic axis has no
 //     ghost points: its lines are rings (faces and stencils wrap), so every
 //     contribution lands on a cell directly.
-// The x and y parts run as two passes (x: sources + x fluxes into a partial
-// sum; y: y fluxes, then the stage combination), each taking grid lines along
+// The x and y parts run as two passes (y: y fluxes into a partial sum; x:
+// sources + x fluxes, then the stage combination), each taking grid lines along
 // its own axis, one wavefront per line and one point and face per lane, with
 // the line's split fluxes (six-point halo) staged in LDS.
 #pragma once
@@ -152,10 +152,10 @@ __device__ __forceinline__ void jacT_row(int c, const JacPt<R>& j, R gamma, R gm
 
 struct VjpPass {
   VjpArgs a;
-  void* Gp;        // partial J_L^T mu in the pass precision (x pass writes, y pass reads)
+  void* Gp;        // partial J_L^T mu in the pass precision (y pass writes, x pass reads)
   int finalize;    // this pass writes out
   double* ghost;   // ghost adjoints of this pass's axis: [2][3][n_across][4]
-  const double* ghost_x;  // y pass: the x pass's ghost adjoints, merged at the x-edge cells
+  const double* ghost_y;  // x pass: the y pass's ghost adjoints, merged at the y-edge cells
 };
 
 // Wavefront-wide lane shift (DPP wave_shr:1 / wave_shl:1): lane l receives
@@ -345,7 +345,9 @@ __global__ __launch_bounds__(64 * NL) void vjp_line_kernel(VjpPass P) {
       P.ghost[(((size_t)side * 3 + layer) * nc + line) * 4 + c] = (double)dU[c];
   }
 
-  // ---- per cell: sources (x pass), then the partial sum or the stage combination
+  // ---- per cell.  The y pass (run first) hands its part to the x pass
+  // through a partial sum; the x pass adds the sources, that partial sum and
+  // the y ghosts' adjoints, and forms the stage combination.
   int ca = k, cb = line;
   bool cact = is_cell;
   double G[4];
@@ -374,10 +376,29 @@ __global__ __launch_bounds__(64 * NL) void vjp_line_kernel(VjpPass P) {
       }
 #pragma unroll
       for (int c = 0; c < 4; ++c) G[c] = (double)(S[c] + dU[c]);
+      if (g.has_y) {
+        const R* gp = static_cast<const R*>(P.Gp);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) G[c] += (double)gp[c * n + q];
+        // y-ghost adjoints whose source is this cell (only cells within three
+        // of a y edge can be sources), in a fixed order
+        const int I = k, J = line;
+        if (g.bc[2] != PERIODIC && (J < NG || J >= g.ny - NG)) {
+          for (int e = 0; e < 6; ++e) {
+            const int side = e / 3, layer = e % 3;
+            const int kk = side == 0 ? -1 - layer : g.ny + layer;
+            bool flip;
+            if (map_index(kk, g.ny, g.bc[2], g.bc[3], flip) != J) continue;
+            const double* gv = P.ghost_y + (((size_t)side * 3 + layer) * g.nx + I) * 4;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) G[c] += (flip && c == 2) ? -gv[c] : gv[c];
+          }
+        }
+      }
     }
   } else {
     // lanes run down columns: transpose the cells' results through LDS so
-    // that the final reads and writes are row segments
+    // that the partial sum is written in row segments
     R(*sT)[NA][NL + 1] = reinterpret_cast<R(*)[NA][NL + 1]>(&sF[0][0][0]);
     static_assert(4 * NA * (NL + 1) <= 8 * NL * LP, "transpose fits in the split-flux storage");
     __syncthreads();  // every wavefront is done with sF
@@ -391,30 +412,14 @@ __global__ __launch_bounds__(64 * NL) void vjp_line_kernel(VjpPass P) {
     ca = a0 + la;
     cact = la < NA && ca < na && cb < nc;
     if (cact) {
-      const size_t q = gidx(ca, cb);
-      const R* gp = static_cast<const R*>(P.Gp);
 #pragma unroll
-      for (int c = 0; c < 4; ++c) G[c] = (double)gp[c * n + q] + (double)sT[c][la][tid % NL];
-      // x-ghost adjoints whose source is this cell (only cells within three
-      // of an x edge can be sources), in a fixed order
-      const int I = cb, J = ca;
-      if (g.bc[0] != PERIODIC && (I < NG || I >= g.nx - NG)) {
-        for (int e = 0; e < 6; ++e) {
-          const int side = e / 3, layer = e % 3;
-          const int kk = side == 0 ? -1 - layer : g.nx + layer;
-          bool flip;
-          if (map_index(kk, g.nx, g.bc[0], g.bc[1], flip) != I) continue;
-          const double* gv = P.ghost_x + (((size_t)side * 3 + layer) * g.ny + J) * 4;
-#pragma unroll
-          for (int c = 0; c < 4; ++c) G[c] += (flip && c == 1) ? -gv[c] : gv[c];
-        }
-      }
+      for (int c = 0; c < 4; ++c) G[c] = (double)sT[c][la][tid % NL];
     }
   }
   if (!cact) return;
   const size_t q = gidx(ca, cb);
   if (!P.finalize) {
-    // (the x pass's partial sum is a value of the pass precision: exact in it)
+    // (the y pass's partial sum is a value of the pass precision: exact in it)
     R* gp = static_cast<R*>(P.Gp);
 #pragma unroll
     for (int c = 0; c < 4; ++c) gp[c * n + q] = (R)G[c];
@@ -422,8 +427,8 @@ __global__ __launch_bounds__(64 * NL) void vjp_line_kernel(VjpPass P) {
   }
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    // the FP64 y pass has the cell's adjoint staged (lane layout: line, point)
-    const double l = STAGE_OWN && sizeof(R) == 8 ? (double)sM[c][cb - b0][ca - a0 + 3] : a.lam[c * n + q];
+    // (in FP64 the x pass holds the cell's adjoint already)
+    const double l = DIR == 0 && sizeof(R) == 8 ? (double)mu[c] : a.lam[c * n + q];
     double o = a.b * __builtin_fma(a.dt, G[c], l);
     if (a.add0) o += a.c0 * a.add0[c * n + q];
     if (a.add1) o += a.c1 * a.add1[c * n + q];

@@ -344,7 +344,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--n", type=int, default=512, help="grid size (n x n)")
-    ap.add_argument("--cpu-steps", type=int, default=40,
+    ap.add_argument("--cpu-steps", type=int, default=100,
                     help="oracle steps timed for the CPU baseline (0: skip)")
     ap.add_argument("--only-fp64", action="store_true", help="skip the FP32-bulk leg")
     ap.add_argument("--adj-n", type=int, default=1024, help="adjoint workload grid (n x n; 0: skip)")

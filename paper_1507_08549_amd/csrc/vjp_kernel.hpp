@@ -214,8 +214,13 @@ __global__ __launch_bounds__(64 * NL) void vjp_line_kernel(VjpPass P) {
   const bool ring = bc_lo == PERIODIC;
   const int cn = DIR == 0 ? 1 : 2;
   const int nta = (na + NA - 1) / NA;
-  const int a0 = (blockIdx.x % nta) * NA;
-  const int b0 = (blockIdx.x / nta) * NL;
+  // Each XCD takes a contiguous run of (segment, line group) tiles: the line
+  // groups next to each other then share an L2, so a 128-byte row that two
+  // groups of 8 FP64 columns split is fetched once, as are the halo points
+  // that neighbouring segments of a line both read.
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int a0 = (tile % nta) * NA;
+  const int b0 = (tile / nta) * NL;
   const size_t n = (size_t)g.nx * g.ny;
   const R gamma = (R)g.gamma, gm1 = (R)g.gm1, eps = (R)g.eps;
   const R alpha = (R)(DIR == 0 ? a.ax : a.ay);

@@ -57,7 +57,9 @@ BCS = [[P, P, P, P], [T, T, T, T], [R, R, R, R], [R, T, R, T], [T, R, P, P]]
 # (116, 58): lines of exactly two and one 58-cell tiles (the ghost points of
 # the last tile's line are its last three lanes)
 # (3, 5): lines shorter than a stencil (periodic lines wrap more than once)
-SHAPES = [(3, 5), (8, 8), (11, 13), (17, 33), (40, 70), (70, 130), (116, 58)]
+# (64, 128): both passes launch a multiple of 8 workgroups (48 and 32), so the
+# tiles are handed to the XCDs in contiguous runs rather than in launch order
+SHAPES = [(3, 5), (8, 8), (11, 13), (17, 33), (40, 70), (70, 130), (116, 58), (64, 128)]
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: f"{s[0]}x{s[1]}")
@@ -132,9 +134,17 @@ def test_step_vjp_gravity_field(torch, hydro, oracle_mod):
     assert _rel_l1(got, want) <= 1e-11
 
 
-def test_step_vjp_fp32_bulk(torch, hydro, oracle_mod):
+@pytest.mark.parametrize("case", ["kh48", "walls64x128"])
+def test_step_vjp_fp32_bulk(torch, hydro, oracle_mod, case):
+    """FP32-bulk stage adjoint against the FP64 reference.  walls64x128: both
+    passes launch a multiple of 8 workgroups (48 and 16: 16 columns per y
+    workgroup in this form) on a grid with reflecting and transmissive edges."""
     from oracle import torch_ref
-    prm, U0 = inputs.kelvin_helmholtz(48, seed=9)
+    if case == "kh48":
+        prm, U0 = inputs.kelvin_helmholtz(48, seed=9)
+    else:
+        prm = inputs.make_params(128, 64, 0.0, 1.0, 0.0, 0.5, [R, T, R, T], 1.4, gy=-0.1)
+        U0 = _random_state(64, 128, seed=21)
     o = oracle_mod.Oracle(prm)
     U0, _, _, _ = o.run(U0, 5)
     dt = o.cfl(U0)

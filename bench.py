@@ -16,8 +16,10 @@ time ratio in FP64 and FP32 keeping every state, and with checkpoints every
 50 steps; central-difference check; FP32-vs-FP64 gradient error), and the potential solver on the polytrope
 density (1024^2, red-black over-relaxation to the relative change 1e-8), the
 level-set flame front (1025^2 corners: advection step and re-distancing), the
-step at 1024^2, 2048^2 and 4096^2 (states beyond the last-level cache), and
-two achievable-peak probes (FP64 fma rate, device copy).
+characteristic-wise reconstruction on the same shear layer (rate, and a few
+steps against the oracle bit for bit), the step at 1024^2, 2048^2 and 4096^2
+(states beyond the last-level cache), and two achievable-peak probes (FP64 fma
+rate, device copy).
 """
 from __future__ import annotations
 
@@ -59,9 +61,9 @@ POISSON_BYTES_PER_CELL_ITER = 8 * 4
 STAGE_TRAFFIC = {
     "sources": ["paper_1507_08549_amd/csrc/stage_kernel.hpp", "paper_1507_08549_amd/csrc/ieee.hpp",
                 "paper_1507_08549_amd/csrc/stage_fp64.hip", "paper_1507_08549_amd/csrc/hydro_internal.hpp"],
-    "sha256": "b62b8d6324de5cf34f93a42f1284348b3d8488d52e53447d2beba5e6a9b84471",
+    "sha256": "391f199656abe7698864bd73113063a5ae8ae9e81bd68b19ab537271b74a946f",
     "n": 512,
-    "bytes_per_launch": (15.194 + 8.489) * 1e6,
+    "bytes_per_launch": (15.192 + 8.489) * 1e6,
     # SQ_INSTS_VALU of the same launch (wavefront instructions), same digest
     "valu_insts_per_launch": 6804486,
 }
@@ -206,6 +208,37 @@ def sweep_leg(torch, hydro, inputs, sizes, steps):
     return out
 
 
+def charwise_leg(torch, hydro, inputs, n, steps, cpu_steps):
+    """The characteristic-wise reconstruction (Roe-averaged eigenvectors at
+    every face, the "WENO-Roe" option of Sect. 2.1) on the same shear layer,
+    FP64: cell-updates/s; on the host, the oracle's characteristic path for a
+    few steps from the same start, compared bit for bit."""
+    prm, U0 = inputs.kelvin_helmholtz(n, seed=2)
+    prm = dict(prm, recon=hydro.CHARACTERISTIC)
+    s = hydro.Solver(prm)
+    U = torch.tensor(U0, dtype=torch.float64, device="cuda")
+    s.run(U, 10)
+    t, _ = timed_run(torch, s, U, steps)
+    res = {"workload": f"kelvin_helmholtz_{n}x{n}", "reconstruction": "characteristic",
+           "precision": "fp64", "steps": steps, "ms_per_step": t * 1e3 / steps,
+           "cell_updates_per_s": n * n * steps / t, "kernel": "stage_kernel<double,16,16,true,true>"}
+    if cpu_steps > 0:
+        import oracle
+        c0 = time.perf_counter()
+        ref, _, _, _ = oracle.Oracle(prm).run(U0, cpu_steps)
+        ct = time.perf_counter() - c0
+        Uc = torch.tensor(U0, dtype=torch.float64, device="cuda")
+        s.run(Uc, cpu_steps)
+        res["oracle_cell_updates_per_s"] = n * n * cpu_steps / ct
+        res["oracle_steps"] = cpu_steps
+        res["bitwise_equal_oracle"] = bool(np.array_equal(Uc.cpu().numpy(), ref))
+    log(f"characteristic: {res['cell_updates_per_s']:.3e} cell-updates/s"
+        + (f", oracle {res['oracle_cell_updates_per_s']:.3e} over {cpu_steps} steps, bitwise "
+           f"{res['bitwise_equal_oracle']}" if cpu_steps > 0 else ""))
+    s.close()
+    return res
+
+
 def configs_leg(torch, hydro, inputs):
     """The other workloads at their full lengths, FP64 and FP32-bulk: rates, the
     FP32 form's relative L1 density error against the FP64 path (which matches
@@ -347,6 +380,10 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=100,
                     help="oracle steps timed for the CPU baseline (0: skip)")
     ap.add_argument("--only-fp64", action="store_true", help="skip the FP32-bulk leg")
+    ap.add_argument("--char-steps", type=int, default=400,
+                    help="steps of the characteristic-reconstruction leg (0: skip)")
+    ap.add_argument("--char-cpu-steps", type=int, default=3,
+                    help="oracle steps of that leg compared bit for bit")
     ap.add_argument("--adj-n", type=int, default=1024, help="adjoint workload grid (n x n; 0: skip)")
     ap.add_argument("--adj-steps", type=int, default=500)
     ap.add_argument("--adj-ckpt", type=int, default=50,
@@ -484,6 +521,11 @@ def main():
         pois = poisson_leg(torch, hydro, inputs, args.poisson_n,
                            args.poisson_cpu_iters if args.cpu_steps > 0 else 0)
 
+    chw = None
+    if args.char_steps > 0:
+        chw = charwise_leg(torch, hydro, inputs, n, args.char_steps,
+                           args.char_cpu_steps if args.cpu_steps > 0 else 0)
+
     lset = None
     if args.ls_n > 0:
         lset = levelset_leg(torch, hydro, inputs, args.ls_n, args.ls_steps, args.cpu_steps > 0)
@@ -518,6 +560,7 @@ def main():
         "sweep": sweep,
         "poisson": pois,
         "levelset": lset,
+        "characteristic": chw,
     }
     print(json.dumps(out), flush=True)
 

@@ -377,6 +377,8 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--n", type=int, default=512, help="grid size (n x n)")
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="timed runs of K steps (the first is the value; all give the median)")
     ap.add_argument("--cpu-steps", type=int, default=100,
                     help="oracle steps timed for the CPU baseline (0: skip)")
     ap.add_argument("--only-fp64", action="store_true", help="skip the FP32-bulk leg")
@@ -429,6 +431,15 @@ def main():
     t64, wall64 = timed_run(torch, s64, U, args.steps)
     v64 = ncell * args.steps / t64
     log(f"fp64: {args.steps} steps in {t64 * 1e3:.2f} ms (wall {wall64 * 1e3:.2f}) -> {v64:.4e} cell-updates/s")
+    # the same K steps timed again (the flow continues), for the spread over runs
+    reps = [v64]
+    for _ in range(max(args.repeats, 1) - 1):
+        t, _ = timed_run(torch, s64, U, args.steps)
+        reps.append(ncell * args.steps / t)
+    repeats = {"runs": len(reps), "median": float(np.median(reps)), "min": min(reps), "max": max(reps)}
+    if len(reps) > 1:
+        log(f"fp64 over {len(reps)} runs of {args.steps} steps: median {repeats['median']:.4e}, "
+            f"min {repeats['min']:.4e}, max {repeats['max']:.4e}")
 
     # stage-kernel average duration: 3 stage launches per step (plus three tiny
     # set-up kernels per call, included, so the estimate is conservative)
@@ -552,6 +563,7 @@ def main():
                      "kernel": "stage_kernel<double,16,16>",
                      "avg_launch_us": stage_s * 1e6, "hbm_gbs_algorithmic": hbm_gbs,
                      "hbm_frac": hbm_gbs / PEAK_HBM_GBS, "issue": issue},
+        "repeats": repeats,
         "cpu_baseline": cpu,
         "fp32_bulk": fp32,
         "adjoint": adj,

@@ -89,6 +89,20 @@ def stage_traffic(n):
     return stage_measured(n, "bytes_per_launch")
 
 
+def host_cpu():
+    """Model name and logical CPU count of the host the oracle ran on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count()}
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -476,6 +490,7 @@ def main():
                "kind": "oracle",
                "sample": f"{args.cpu_steps} SSP-RK3 steps of the same {n}x{n} shear layer, "
                          f"single-threaded C oracle, {ct:.1f} s"}
+        cpu["host"] = host_cpu()
         log(f"oracle: {cpu['value']:.4e} cell-updates/s ({ct:.1f} s)")
         Uc = torch.tensor(U0, dtype=torch.float64, device="cuda")
         s64.run(Uc, args.cpu_steps)

@@ -35,3 +35,10 @@ def test_counter_figures_follow_the_source_digest(monkeypatch):
     monkeypatch.setitem(b.STAGE_TRAFFIC, "sha256", "0" * 64)      # other sources
     assert b.stage_measured(n, "bytes_per_launch") is None
     assert b.stage_measured(n, "valu_insts_per_launch") is None
+
+
+def test_host_cpu_description():
+    b = _bench_module()
+    h = b.host_cpu()
+    assert set(h) == {"model", "logical_cpus"}
+    assert h["logical_cpus"] is None or h["logical_cpus"] >= 1

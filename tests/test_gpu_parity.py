@@ -285,6 +285,27 @@ def test_fp32_bulk_rhs_vs_oracle(torch, hydro, oracle_mod):
     assert err <= 1e-5, err
 
 
+@pytest.mark.parametrize("case", ["polytrope128", "rt64x256"])
+def test_fp32_bulk_gravity_vs_oracle(torch, hydro, oracle_mod, case):
+    """FP32-bulk with gravity over ten steps against the FP64 oracle, same
+    bound as the shear layer: the polytrope (cylindrical, gravity field,
+    density floor) and the heavy-over-light layer (uniform gravity,
+    reflecting walls)."""
+    if case == "polytrope128":
+        prm, U0, grav = inputs.polytrope(128)
+    else:
+        (prm, U0), grav = inputs.rayleigh_taylor(64, 256), None
+    want, _, _, _ = oracle_mod.Oracle(prm, gravity=grav).run(U0, 10)
+    g = None if grav is None else _dev(torch, grav)
+    s = hydro.Solver(prm, gravity=g, precision=hydro.FP32_BULK)
+    U = _dev(torch, U0)
+    s.run(U, 10)
+    got = U.cpu().numpy()
+    for c in (0, 3):
+        err = np.abs(got[c] - want[c]).sum() / np.abs(want[c]).sum()
+        assert err <= 1e-6, (c, err)
+
+
 def test_fp32_bulk_sod_vs_oracle(torch, hydro, oracle_mod):
     prm, U0 = inputs.sod(400)
     want, t, dts, _ = oracle_mod.Oracle(prm).run(U0, 100000, t_end=0.2)

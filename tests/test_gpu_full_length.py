@@ -1,9 +1,12 @@
-"""The shear-layer workload at its full length (512^2, 2000 SSP-RK3 steps with
-the device time step) against the oracle, compared every 100 steps: bit for
-bit in FP64, and the FP32-bulk form's relative L1 density error within 5e-6
-(1.5e-6 measured; it grows with the flow's instability from ~1e-7).  The
-oracle needs about four minutes for it, so the test runs only when
-HYDRO_FULL_LENGTH=1 is set."""
+"""The workloads at their full lengths against the oracle, with the device time
+step: the shear layer (512^2, 2000 SSP-RK3 steps, compared every 100 steps:
+bit for bit in FP64, and the FP32-bulk form's relative L1 density error
+within 5e-6; 1.5e-6 measured, it grows with the flow's instability from
+~1e-7), the heavy-over-light layer (256 x 1024, 5000 steps, every 250) and
+the polytrope (1024^2 in (r, z) with its gravity field and floor, 1000 steps,
+every 50), both bit for bit in FP64.  The oracle needs about four, ten and
+nine minutes for them, so the tests run only when HYDRO_FULL_LENGTH=1 is
+set (one per call within a ten-minute limit)."""
 import os
 
 import numpy as np
@@ -13,7 +16,7 @@ from paper_1507_08549_amd import inputs
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow,
               pytest.mark.skipif(os.environ.get("HYDRO_FULL_LENGTH") != "1",
-                                 reason="four minutes of oracle time; set HYDRO_FULL_LENGTH=1")]
+                                 reason="minutes of oracle time; set HYDRO_FULL_LENGTH=1")]
 
 
 def test_shear_layer_2000_steps(oracle_mod):
@@ -34,3 +37,25 @@ def test_shear_layer_2000_steps(oracle_mod):
         err = np.abs(U32.cpu().numpy()[0] - W[0]).sum() / np.abs(W[0]).sum()
         print(f"{100 * (c + 1)} steps: fp32 L1 rel density error {err:.3e}", flush=True)
         assert err < 5e-6
+
+
+@pytest.mark.parametrize("case", ["rayleigh_taylor_5000", "polytrope_1000"])
+def test_gravity_workloads_full_length(oracle_mod, case):
+    import torch
+    from paper_1507_08549_amd import hydro
+    if case == "rayleigh_taylor_5000":
+        (prm, U0), grav, n, every = inputs.rayleigh_taylor(), None, 5000, 250
+    else:
+        prm, U0, grav = inputs.polytrope(1024)
+        n, every = 1000, 50
+    g = None if grav is None else torch.tensor(grav, device="cuda")
+    s = hydro.Solver(prm, gravity=g)
+    U = torch.tensor(U0, device="cuda")
+    o = oracle_mod.Oracle(prm, gravity=grav)
+    W, t_o, t_g = U0.copy(), 0.0, 0.0
+    for done in range(every, n + 1, every):
+        W, t_o, _, _ = o.run(W, every, t0=t_o)
+        _, t_g, _, _ = s.run(U, every, t0=t_g)
+        assert t_g == t_o
+        assert np.array_equal(U.cpu().numpy(), W), f"not bitwise after {done} steps"
+        print(f"{case}: bitwise after {done} steps", flush=True)

@@ -2,11 +2,12 @@
 step: the shear layer (512^2, 2000 SSP-RK3 steps, compared every 100 steps:
 bit for bit in FP64, and the FP32-bulk form's relative L1 density error
 within 5e-6; 1.5e-6 measured, it grows with the flow's instability from
-~1e-7), the heavy-over-light layer (256 x 1024, 5000 steps, every 250) and
-the polytrope (1024^2 in (r, z) with its gravity field and floor, 1000 steps,
-every 50), both bit for bit in FP64.  The oracle needs about four, ten and
-nine minutes for them, so the tests run only when HYDRO_FULL_LENGTH=1 is
-set (one per call within a ten-minute limit)."""
+~1e-7), the heavy-over-light layer (256 x 1024, 5000 steps, every 250), the
+polytrope (1024^2 in (r, z) with its gravity field and floor, 1000 steps,
+every 50) and the adjoint workload's forward rollout (sine-mode shear layer
+1024^2, 500 steps, every 50), all bit for bit in FP64.  The oracle needs
+about four, ten, nine and five minutes for them, so the tests run only when
+HYDRO_FULL_LENGTH=1 is set (one per call within a ten-minute limit)."""
 import os
 
 import numpy as np
@@ -39,15 +40,18 @@ def test_shear_layer_2000_steps(oracle_mod):
         assert err < 5e-6
 
 
-@pytest.mark.parametrize("case", ["rayleigh_taylor_5000", "polytrope_1000"])
-def test_gravity_workloads_full_length(oracle_mod, case):
+@pytest.mark.parametrize("case", ["rayleigh_taylor_5000", "polytrope_1000", "kh_sine_500"])
+def test_other_workloads_full_length(oracle_mod, case):
     import torch
     from paper_1507_08549_amd import hydro
     if case == "rayleigh_taylor_5000":
         (prm, U0), grav, n, every = inputs.rayleigh_taylor(), None, 5000, 250
-    else:
+    elif case == "polytrope_1000":
         prm, U0, grav = inputs.polytrope(1024)
         n, every = 1000, 50
+    else:  # the adjoint workload's forward rollout
+        prm = inputs.kh_sine_params(1024)
+        U0, grav, n, every = inputs.kh_sine_state(inputs.kh_sine_amplitudes(), prm), None, 500, 50
     g = None if grav is None else torch.tensor(grav, device="cuda")
     s = hydro.Solver(prm, gravity=g)
     U = torch.tensor(U0, device="cuda")

@@ -10,7 +10,9 @@ Contents
 * ``hydro_oracle.c`` -- plain C: one SSP-RK3 step of Eq. euler2D (Sect. 2.1)
   with fifth-order finite-difference WENO on a global Lax-Friedrichs split,
   the CFL step of Sect. 5.3, compensated totals.  Built by :func:`build` with
-  gcc ``-O2 -ffp-contract=off``.
+  gcc ``-O2 -ffp-contract=off -fopenmp``: the loops over rows, columns and
+  cells are shared among threads (:func:`set_threads`) with results that are
+  bit for bit the same for any thread count.
 * ``poisson_oracle.c`` -- plain C: the potential of Sect. 2.1 by red-black
   successive over-relaxation in (r, z), reflecting axis and plane, Roche
   outer values; the acceleration -grad Phi.
@@ -43,7 +45,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         cmd = ["gcc", "-O2", "-mfma", "-ffp-contract=off", "-fno-fast-math", "-std=c99",
-               "-fPIC", "-shared", "-Wall", "-o", tmp, *_SRCS, "-lm"]
+               "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", tmp, *_SRCS, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -98,8 +100,9 @@ def _load():
         lib.orc_step.argtypes = [pp, dp, dp, ctypes.c_double, dp, dp]
         lib.orc_run.argtypes = [pp, dp, dp, ctypes.c_int, ctypes.c_double, dp, dp, dp]
         lib.orc_sums.argtypes = [pp, dp, dp]
+        lib.orc_set_threads.argtypes = [ctypes.c_int]
         for f in ("orc_alpha", "orc_cfl", "orc_rhs", "orc_step", "orc_run", "orc_sums",
-                  "orc_params_size"):
+                  "orc_params_size", "orc_set_threads"):
             getattr(lib, f).restype = ctypes.c_int
         assert lib.orc_params_size() == ctypes.sizeof(_Params)
         lib.orc_char_eig.argtypes = [dp, dp, ctypes.c_int, ctypes.c_double, dp, dp]
@@ -127,6 +130,18 @@ def _load():
         assert lib.orc_ls_params_size() == ctypes.sizeof(_LsParams)
         _lib = lib
     return _lib
+
+
+def set_threads(n: int) -> int:
+    """Threads for the hydro oracle's parallel loops (n >= 1); returns the
+    number in effect.  The default is OpenMP's (OMP_NUM_THREADS, else every
+    core).  Results do not depend on it."""
+    return int(_load().orc_set_threads(int(n)))
+
+
+def threads() -> int:
+    """Threads the hydro oracle's parallel loops use now."""
+    return int(_load().orc_set_threads(0))
 
 
 def _ptr(a):

@@ -22,6 +22,12 @@
  * Plain, slow and explicit: every stage copies the state into an array
  * padded with three ghost layers, computes primitives, split fluxes,
  * reconstructions and divergences in separate loops, one cell at a time.
+ * Built with -fopenmp, the loops over rows (x sweep), columns (y sweep) and
+ * cells are shared among threads.  Each row, column or cell is computed by
+ * the same operations whichever thread takes it, and the only reductions are
+ * maxima (exact, order-free) and an error flag, so the result is bit for bit
+ * the same for any number of threads.  The compensated totals (orc_sums)
+ * stay sequential: their rounding depends on the order.
  *
  * Readings of the paper (the paper prints no WENO formula and no rounding
  * rules; these choices are ours and are listed in the design notes):
@@ -56,6 +62,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define NG 3 /* ghost layers: the five-point WENO stencil reaches 3 cells past a face */
 
@@ -196,13 +205,16 @@ static int ghost_src(int g, int n, int bc_lo, int bc_hi, double *flip) {
 
 static void fill_padded(const orc_params *p, const double *V, padded_t *P) {
   const int nx = p->nx, ny = p->ny;
-  size_t total = (size_t)4 * P->py * P->px;
-  for (size_t k = 0; k < total; ++k) P->a[k] = NAN; /* corners stay NaN: never read */
+  const long total = (long)4 * P->py * P->px;
+#pragma omp parallel for schedule(static)
+  for (long k = 0; k < total; ++k) P->a[k] = NAN; /* corners stay NaN: never read */
+#pragma omp parallel for collapse(2) schedule(static)
   for (int c = 0; c < 4; ++c)
     for (int j = 0; j < ny; ++j)
       for (int i = 0; i < nx; ++i)
         *pad_at(P, c, j, i) = V[((size_t)c * ny + j) * nx + i];
   /* x ghosts, interior rows */
+#pragma omp parallel for schedule(static)
   for (int j = 0; j < ny; ++j)
     for (int g = -NG; g < nx + NG; ++g) {
       if (g >= 0 && g < nx) continue;
@@ -235,10 +247,11 @@ static void fill_padded(const orc_params *p, const double *V, padded_t *P) {
 int orc_alpha(const orc_params *p, const double *V, double out[3]) {
   int rc = check_params(p);
   if (rc) return rc;
-  const size_t n = (size_t)p->nx * p->ny;
+  const long n = (long)p->nx * p->ny;
   double ax = 0.0, ay = 0.0, sm = 0.0;
   int bad = 0;
-  for (size_t k = 0; k < n; ++k) {
+#pragma omp parallel for schedule(static) reduction(max : ax, ay, sm) reduction(| : bad)
+  for (long k = 0; k < n; ++k) {
     double r = V[k], mx = V[n + k], my = V[2 * n + k], E = V[3 * n + k];
     prim_t w = cons_to_prim(r, mx, my, E, p->gamma);
     if (!(r > 0.0) || !(w.p > 0.0) || !isfinite(w.c)) bad = 1;
@@ -404,82 +417,100 @@ int orc_rhs(const orc_params *p, const double *gravity, const double *V,
   P.a = (double *)malloc(sizeof(double) * 4 * (size_t)P.px * P.py);
   double *Dx = (double *)calloc(4 * n, sizeof(double));
   double *Dy = (double *)calloc(4 * n, sizeof(double));
-  int len = (nx > ny ? nx : ny) + 2 * NG;
-  double *fp = (double *)malloc(sizeof(double) * 4 * len);
-  double *fm = (double *)malloc(sizeof(double) * 4 * len);
-  double *Fh = (double *)malloc(sizeof(double) * 4 * (len + 1));
-  if (!P.a || !Dx || !Dy || !fp || !fm || !Fh) {
-    free(P.a); free(Dx); free(Dy); free(fp); free(fm); free(Fh);
+  if (!P.a || !Dx || !Dy) {
+    free(P.a); free(Dx); free(Dy);
     return ORC_E_NOMEM;
   }
   fill_padded(p, V, &P);
-  int status = ORC_OK;
+  int status = ORC_OK, nomem = 0;
+  const int len = (nx > ny ? nx : ny) + 2 * NG;
 
-  /* x sweep, one interior row at a time.  Padded point k <-> cell k - NG.
-   * Face f (0..nx) sits between cells f-1 and f. */
-  for (int j = 0; j < ny; ++j) {
-    for (int k = 0; k < nx + 2 * NG; ++k) {
-      double U[4], a[4], b[4];
-      for (int c = 0; c < 4; ++c) U[c] = *pad_at(&P, c, j, k - NG);
-      split_flux(U, p->gamma, ax, 0, a, b);
-      for (int c = 0; c < 4; ++c) { fp[4 * k + c] = a[c]; fm[4 * k + c] = b[c]; }
-    }
-    for (int f = 0; f <= nx; ++f) {
-      int i = f - 1 + NG; /* padded index of the cell left of the face */
-      if (p->recon == 1) {
-        double Ul[4], Ur[4];
-        for (int c = 0; c < 4; ++c) {
-          Ul[c] = *pad_at(&P, c, j, i - NG);
-          Ur[c] = *pad_at(&P, c, j, i + 1 - NG);
-        }
-        if (char_face(fp, fm, i, Ul, Ur, 0, p->gamma, eps, &Fh[4 * f])) status = ORC_E_UNPHYSICAL;
-        continue;
-      }
-      for (int c = 0; c < 4; ++c) {
-        Fh[4 * f + c] = orc_weno5_face(fp[4 * (i - 2) + c], fp[4 * (i - 1) + c], fp[4 * i + c],
-                                       fp[4 * (i + 1) + c], fp[4 * (i + 2) + c],
-                                       fm[4 * (i + 3) + c], fm[4 * (i + 2) + c], fm[4 * (i + 1) + c],
-                                       fm[4 * i + c], fm[4 * (i - 1) + c], eps);
-      }
-    }
-    for (int i = 0; i < nx; ++i)
-      for (int c = 0; c < 4; ++c)
-        Dx[((size_t)c * ny + j) * nx + i] = (Fh[4 * (i + 1) + c] - Fh[4 * i + c]) * idx;
-  }
+#pragma omp parallel reduction(min : status) reduction(| : nomem)
+  {
+    /* line buffers of this thread: split fluxes of one row or column and its face values */
+    double *fp = (double *)malloc(sizeof(double) * 4 * len);
+    double *fm = (double *)malloc(sizeof(double) * 4 * len);
+    double *Fh = (double *)malloc(sizeof(double) * 4 * (len + 1));
+    const int have = fp && fm && Fh;
+    if (!have) nomem = 1;
 
-  /* y sweep, one interior column at a time (skipped in the 1D limit). */
-  if (ny > 1)
-    for (int i = 0; i < nx; ++i) {
-      for (int k = 0; k < ny + 2 * NG; ++k) {
+    /* x sweep, one interior row at a time.  Padded point k <-> cell k - NG.
+     * Face f (0..nx) sits between cells f-1 and f. */
+#pragma omp for schedule(static)
+    for (int j = 0; j < ny; ++j) {
+      if (!have) continue;
+      for (int k = 0; k < nx + 2 * NG; ++k) {
         double U[4], a[4], b[4];
-        for (int c = 0; c < 4; ++c) U[c] = *pad_at(&P, c, k - NG, i);
-        split_flux(U, p->gamma, ay, 1, a, b);
+        for (int c = 0; c < 4; ++c) U[c] = *pad_at(&P, c, j, k - NG);
+        split_flux(U, p->gamma, ax, 0, a, b);
         for (int c = 0; c < 4; ++c) { fp[4 * k + c] = a[c]; fm[4 * k + c] = b[c]; }
       }
-      for (int f = 0; f <= ny; ++f) {
-        int jj = f - 1 + NG;
+      for (int f = 0; f <= nx; ++f) {
+        int i = f - 1 + NG; /* padded index of the cell left of the face */
         if (p->recon == 1) {
           double Ul[4], Ur[4];
           for (int c = 0; c < 4; ++c) {
-            Ul[c] = *pad_at(&P, c, jj - NG, i);
-            Ur[c] = *pad_at(&P, c, jj + 1 - NG, i);
+            Ul[c] = *pad_at(&P, c, j, i - NG);
+            Ur[c] = *pad_at(&P, c, j, i + 1 - NG);
           }
-          if (char_face(fp, fm, jj, Ul, Ur, 1, p->gamma, eps, &Fh[4 * f])) status = ORC_E_UNPHYSICAL;
+          if (char_face(fp, fm, i, Ul, Ur, 0, p->gamma, eps, &Fh[4 * f])) status = ORC_E_UNPHYSICAL;
           continue;
         }
         for (int c = 0; c < 4; ++c) {
-          Fh[4 * f + c] = orc_weno5_face(fp[4 * (jj - 2) + c], fp[4 * (jj - 1) + c], fp[4 * jj + c],
-                                         fp[4 * (jj + 1) + c], fp[4 * (jj + 2) + c],
-                                         fm[4 * (jj + 3) + c], fm[4 * (jj + 2) + c], fm[4 * (jj + 1) + c],
-                                         fm[4 * jj + c], fm[4 * (jj - 1) + c], eps);
+          Fh[4 * f + c] = orc_weno5_face(fp[4 * (i - 2) + c], fp[4 * (i - 1) + c], fp[4 * i + c],
+                                         fp[4 * (i + 1) + c], fp[4 * (i + 2) + c],
+                                         fm[4 * (i + 3) + c], fm[4 * (i + 2) + c], fm[4 * (i + 1) + c],
+                                         fm[4 * i + c], fm[4 * (i - 1) + c], eps);
         }
       }
-      for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i)
         for (int c = 0; c < 4; ++c)
-          Dy[((size_t)c * ny + j) * nx + i] = (Fh[4 * (j + 1) + c] - Fh[4 * j + c]) * idy;
+          Dx[((size_t)c * ny + j) * nx + i] = (Fh[4 * (i + 1) + c] - Fh[4 * i + c]) * idx;
     }
 
+    /* y sweep, one interior column at a time (skipped in the 1D limit). */
+    if (ny > 1) {
+#pragma omp for schedule(static)
+      for (int i = 0; i < nx; ++i) {
+        if (!have) continue;
+        for (int k = 0; k < ny + 2 * NG; ++k) {
+          double U[4], a[4], b[4];
+          for (int c = 0; c < 4; ++c) U[c] = *pad_at(&P, c, k - NG, i);
+          split_flux(U, p->gamma, ay, 1, a, b);
+          for (int c = 0; c < 4; ++c) { fp[4 * k + c] = a[c]; fm[4 * k + c] = b[c]; }
+        }
+        for (int f = 0; f <= ny; ++f) {
+          int jj = f - 1 + NG;
+          if (p->recon == 1) {
+            double Ul[4], Ur[4];
+            for (int c = 0; c < 4; ++c) {
+              Ul[c] = *pad_at(&P, c, jj - NG, i);
+              Ur[c] = *pad_at(&P, c, jj + 1 - NG, i);
+            }
+            if (char_face(fp, fm, jj, Ul, Ur, 1, p->gamma, eps, &Fh[4 * f])) status = ORC_E_UNPHYSICAL;
+            continue;
+          }
+          for (int c = 0; c < 4; ++c) {
+            Fh[4 * f + c] = orc_weno5_face(fp[4 * (jj - 2) + c], fp[4 * (jj - 1) + c], fp[4 * jj + c],
+                                           fp[4 * (jj + 1) + c], fp[4 * (jj + 2) + c],
+                                           fm[4 * (jj + 3) + c], fm[4 * (jj + 2) + c], fm[4 * (jj + 1) + c],
+                                           fm[4 * jj + c], fm[4 * (jj - 1) + c], eps);
+          }
+        }
+        for (int j = 0; j < ny; ++j)
+          for (int c = 0; c < 4; ++c)
+            Dy[((size_t)c * ny + j) * nx + i] = (Fh[4 * (j + 1) + c] - Fh[4 * j + c]) * idy;
+      }
+    }
+    free(fp); free(fm); free(Fh);
+  }
+  if (nomem) {
+    free(P.a); free(Dx); free(Dy);
+    return ORC_E_NOMEM;
+  }
+
   /* Sources of Eq. euler2D and L = S - (Dx + Dy). */
+#pragma omp parallel for schedule(static)
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i) {
       size_t k = (size_t)j * nx + i;
@@ -507,7 +538,7 @@ int orc_rhs(const orc_params *p, const double *gravity, const double *V,
       }
     }
 
-  free(P.a); free(Dx); free(Dy); free(fp); free(fm); free(Fh);
+  free(P.a); free(Dx); free(Dy);
   return status;
 }
 
@@ -550,13 +581,15 @@ int orc_step(const orc_params *p, const double *gravity, double *U, double dt,
     if (alpha_out) { alpha_out[2 * s] = ax; alpha_out[2 * s + 1] = ay; }
     rc = orc_rhs(p, gravity, V, ax, ay, L);
     if (rc) { status = rc; break; }
-    for (size_t q = 0; q < n4; ++q) W[q] = fma(cb[s], fma(dt, L[q], V[q] - U[q]), U[q]);
+#pragma omp parallel for schedule(static)
+    for (long q = 0; q < (long)n4; ++q) W[q] = fma(cb[s], fma(dt, L[q], V[q] - U[q]), U[q]);
     if (p->rho_floor > 0.0) {
       /* atmosphere (Sect. 5.3 enforces a minimum density, the atmosphere's):
        * rho < rho_floor -> the atmosphere state at rest; then, for the ideal
        * gas, p < p_floor -> internal energy raised to the atmosphere's
        * pressure with rho and m kept. */
-      for (size_t k = 0; k < n; ++k) {
+#pragma omp parallel for schedule(static)
+      for (long k = 0; k < (long)n; ++k) {
         if (W[k] < p->rho_floor) {
           W[k] = p->rho_floor;
           W[n + k] = 0.0;
@@ -568,10 +601,13 @@ int orc_step(const orc_params *p, const double *gravity, double *U, double dt,
           W[3 * n + k] = p->p_floor / (p->gamma - 1.0) + 0.5 * (W[n + k] * w.u + W[2 * n + k] * w.v);
       }
     }
-    for (size_t k = 0; k < n; ++k) {
+    int unphys = 0;
+#pragma omp parallel for schedule(static) reduction(| : unphys)
+    for (long k = 0; k < (long)n; ++k) {
       prim_t w = cons_to_prim(W[k], W[n + k], W[2 * n + k], W[3 * n + k], p->gamma);
-      if (!(W[k] > 0.0) || !(w.p > 0.0) || !isfinite(w.c)) status = ORC_E_UNPHYSICAL;
+      if (!(W[k] > 0.0) || !(w.p > 0.0) || !isfinite(w.c)) unphys = 1;
     }
+    if (unphys) status = ORC_E_UNPHYSICAL;
     double *t = V; V = W; W = t;
   }
   if (status == ORC_OK) memcpy(U, V, sizeof(double) * n4);
@@ -630,6 +666,18 @@ int orc_sums(const orc_params *p, const double *U, double out[4]) {
     out[c] = s + comp;
   }
   return ORC_OK;
+}
+
+/* Number of threads the parallel loops use (n >= 1); returns the number in
+ * effect (1 without OpenMP). */
+int orc_set_threads(int nthreads) {
+#ifdef _OPENMP
+  if (nthreads >= 1) omp_set_num_threads(nthreads);
+  return omp_get_max_threads();
+#else
+  (void)nthreads;
+  return 1;
+#endif
 }
 
 /* Size of the parameter struct, so the binding can check its mirror. */

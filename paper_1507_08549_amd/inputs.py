@@ -23,6 +23,12 @@ Workloads
 
 Random draws use ``numpy.random.default_rng(seed)``; ``uniform(-1, 1,
 (ny, nx))`` is drawn in C order (row = y).
+
+The benchmark workloads' states are bit-reproducible on any x86-64 host:
+their transcendental values come from the C library one value at a time
+(:func:`_libm`), not from numpy's vectorised kernels (which differ with the
+CPU's vector extensions), and the sine-mode sum runs in a fixed order instead
+of through a BLAS product (whose summation order depends on the CPU).
 """
 from __future__ import annotations
 
@@ -33,6 +39,19 @@ import numpy as np
 
 PERIODIC, TRANSMISSIVE, REFLECTING = 0, 1, 2
 CARTESIAN, CYLINDRICAL = 0, 1
+
+
+def _libm(f, a):
+    """f (a scalar function of the math module) applied to every element of a."""
+    a = np.asarray(a, dtype=np.float64)
+    return np.fromiter((f(float(x)) for x in a.ravel()), dtype=np.float64, count=a.size).reshape(a.shape)
+
+
+def _libm_pow(a, e):
+    a = np.asarray(a, dtype=np.float64)
+    e = float(e)
+    return np.fromiter((math.pow(float(x), e) for x in a.ravel()), dtype=np.float64,
+                       count=a.size).reshape(a.shape)
 
 
 def make_params(nx, ny, xlo, xhi, ylo, yhi, bc, gamma, cfl=0.5, eps=1e-6,
@@ -116,7 +135,9 @@ def rayleigh_taylor(nx=256, ny=1024, seed=3, gamma=1.4, cfl=0.5, g=-0.1):
     rho = np.where(Y > 1.0, 2.0, 1.0)
     p = 2.5 + g * rho * (Y - 1.0)
     rng = np.random.default_rng(seed)
-    v = 0.01 * (1.0 + np.cos(4.0 * np.pi * X)) * (1.0 + np.cos(np.pi * (Y - 1.0))) / 4.0
+    cx = _libm(math.cos, 4.0 * np.pi * x)[None, :]
+    cy = _libm(math.cos, np.pi * (y - 1.0))[:, None]
+    v = 0.01 * (1.0 + cx) * (1.0 + cy) / 4.0
     v = v + 1e-4 * rng.uniform(-1.0, 1.0, (ny, nx))
     return prm, state_from_primitive(rho, 0.0, v, p, gamma)
 
@@ -184,12 +205,12 @@ def polytrope(n=1024, seed=4, poly_n=3.0, K=1.0, rho_c=1.0, G=1.0, rho_floor=1e-
     inside = xi < xi1
     theta = np.where(inside, np.interp(xi, xi_t, th_t), 0.0)
     dtheta = np.where(inside, np.interp(xi, xi_t, ph_t), ph_t[-1])
-    rho_le = rho_c * np.maximum(theta, 0.0) ** poly_n
+    rho_le = rho_c * _libm_pow(np.maximum(theta, 0.0), poly_n)
     rng = np.random.default_rng(seed)
     pert = 1.0 + noise * rng.uniform(-1.0, 1.0, (n, n))
     dense = rho_le > rho_floor
     rho = np.where(dense, rho_le * pert, rho_floor)
-    p = K * np.maximum(rho_le, rho_floor) ** gamma
+    p = K * _libm_pow(np.maximum(rho_le, rho_floor), gamma)
     xi_m = np.where(inside, xi, xi1)
     M = 4.0 * math.pi * a ** 3 * rho_c * xi_m ** 2 * np.abs(dtheta)
     gmag = -G * M / (Rad * Rad)
@@ -217,21 +238,31 @@ def kh_sine_state(a, params, xp=None):
     rho_np = np.where(inner, 2.0, 1.0)
     u_np = np.where(inner, 0.5, -0.5)
     k = np.arange(1, len(a) + 1)
-    basis = np.sin(2.0 * np.pi * np.outer(k, x))  # (K, nx)
+    basis = _libm(math.sin, 2.0 * np.pi * np.outer(k, x))  # (K, nx)
     try:
         import torch
         is_torch = isinstance(a, torch.Tensor)
     except ImportError:  # pragma: no cover
         is_torch = False
+    # v = a_1 B_1 + a_2 B_2 + ... summed in this order (elementwise products
+    # and sums: the same values from numpy and from torch on any device)
     if not is_torch:
-        v = (np.asarray(a, dtype=np.float64) @ basis)[None, :] * np.ones((ny, 1))
+        an = np.asarray(a, dtype=np.float64)
+        v = an[0] * basis[0]
+        for m in range(1, len(an)):
+            v = v + an[m] * basis[m]
+        v = v[None, :] * np.ones((ny, 1))
         return state_from_primitive(rho_np, u_np, v, 2.5, gamma)
     import torch
     dev, dt = a.device, torch.float64
     rho = torch.as_tensor(rho_np, device=dev, dtype=dt)
     u = torch.as_tensor(u_np, device=dev, dtype=dt)
     B = torch.as_tensor(basis, device=dev, dtype=dt)
-    v = (a.to(dt) @ B).unsqueeze(0).expand(ny, nx)
+    ad = a.to(dt)
+    vx = ad[0] * B[0]
+    for m in range(1, ad.shape[0]):
+        vx = vx + ad[m] * B[m]
+    v = vx.unsqueeze(0).expand(ny, nx)
     E = 2.5 / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)
     return torch.stack([rho, rho * u, rho * v, E]).contiguous()
 

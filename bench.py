@@ -174,10 +174,30 @@ def fd_check(torch, inputs, s, a_np, sched, comps, h=1e-7):
     return np.array(out)
 
 
-def probes(torch, solver):
-    """Achievable-peak references: the FP64 fma rate (library probe kernel) and
-    a 1 GiB device-to-device copy (read + written bytes per second)."""
-    fma = solver.probe_fma(20000)
+PROBE_LIB = os.path.join(ROOT, "paper_1507_08549_amd", "libhydro_probe.so")
+
+
+def fma_probe_rate(torch, iters=20000):
+    """Achievable FP64 fma rate (flop/s) of the current device, from the
+    measurement library's probe kernel (csrc/probe.h), on torch's current
+    stream."""
+    import ctypes
+    if not os.path.exists(PROBE_LIB):
+        raise RuntimeError(f"{PROBE_LIB} is missing: build it with paper_1507_08549_amd.build.build()")
+    lib = ctypes.CDLL(PROBE_LIB)
+    lib.hydro_probe_fma_rate.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
+    lib.hydro_probe_fma_rate.restype = ctypes.c_int
+    r = ctypes.c_double()
+    rc = lib.hydro_probe_fma_rate(int(iters), torch.cuda.current_stream().cuda_stream, ctypes.byref(r))
+    if rc != 0:
+        raise RuntimeError(f"hydro_probe_fma_rate failed ({rc})")
+    return r.value
+
+
+def probes(torch):
+    """Achievable-peak references: the FP64 fma rate (probe kernel) and a 1 GiB
+    device-to-device copy (read + written bytes per second)."""
+    fma = fma_probe_rate(torch, 20000)
     nel = (1 << 30) // 8
     src = torch.ones(nel, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
@@ -535,7 +555,7 @@ def main():
             f"{adj['ratio_fp64_ckpt']:.2f} / {adj['ratio_fp32_ckpt']:.2f}; FD rel err {fd_err:.2e}, "
             f"fp32 grad rel err {adj['grad_rel_err_fp32_vs_fp64']:.2e}")
 
-    prb = None if args.no_probes else probes(torch, s64)
+    prb = None if args.no_probes else probes(torch)
     sweep = None
     if args.sweep:
         sweep = sweep_leg(torch, hydro, inputs, [int(v) for v in args.sweep.split(",") if v], args.sweep_steps)

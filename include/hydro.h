@@ -258,15 +258,14 @@ int hydro_ls_front(hydro_ctx* ctx, const double* S, double* pts, int64_t cap, in
  * search), then runs asynchronously. */
 int hydro_ls_redistance(hydro_ctx* ctx, double* S, double* dist, int64_t* npoints);
 
-/* Measurement aid: the achievable FP64 vector fma rate of the context's device
- * (eight independent fma chains per work item, 8 workgroups of 256 per compute
- * unit, iters rounds; an fma counts 2 flops), timed with events on the
- * context's stream.  *flops_per_s receives the rate.  Synchronises. */
-int hydro_probe_fma(hydro_ctx* ctx, int32_t iters, double* flops_per_s);
-
-/* Totals of rho, m_x, m_y, E times the cell volume (dx dy; 2 pi r_i dx dy in
- * cylindrical geometry), with compensated (Neumaier) summation in a fixed
- * order.  Synchronises; out_host[4] receives them. */
+/* Conserved totals: the integrals of rho, m_x, m_y and E over the grid, i.e.
+ * the mass, momentum and energy whose relative changes Delta M / M and
+ * Delta E / E the paper reports for its Gresho vortex test (Sect. 5.2, Table
+ * Test2D_test1).  Each value times the cell volume (dx dy; 2 pi r_i dx dy in
+ * cylindrical geometry, r_i = xlo + (i + 1/2) dx), summed with compensated
+ * (Neumaier) summation over a fixed partition and tree, so the result does not
+ * depend on the launch.  U: device [4][ny][nx].  Synchronises; out_host[4]
+ * receives the four totals. */
 int hydro_sums(hydro_ctx* ctx, const double* U, double out_host[4]);
 
 /* Synchronise and return (then clear) the sticky UNPHYSICAL flag. */

@@ -18,6 +18,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhydro.so")
+# measurement aid, kept out of the solver library (csrc/probe.h)
+PROBE_LIB = os.path.join(HERE, "libhydro_probe.so")
+PROBE_UNITS = {"probe.hip": []}
 ARCH = os.environ.get("HYDRO_OFFLOAD_ARCH", "gfx950")
 
 # translation unit -> extra flags
@@ -28,7 +31,6 @@ UNITS = {
     "reduce.hip": ["-ffp-contract=off"],
     "poisson.hip": ["-ffp-contract=off"],
     "levelset.hip": ["-ffp-contract=off"],
-    "probe.hip": [],
     "vjp_fp64.hip": [],
     "vjp_fp32.hip": [],
 }
@@ -60,14 +62,16 @@ def build(verbose: bool = False) -> str:
             print(r.stderr, file=sys.stderr)
         return obj
 
-    with ThreadPoolExecutor(max_workers=min(len(UNITS), 8)) as ex:
-        objs = list(ex.map(compile_one, UNITS.items()))
-    tmp = LIB + ".tmp"
-    cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    units = list(UNITS.items()) + list(PROBE_UNITS.items())
+    with ThreadPoolExecutor(max_workers=min(len(units), 8)) as ex:
+        objs = dict(zip([u for u, _ in units], ex.map(compile_one, units)))
+    for lib, names in ((LIB, UNITS), (PROBE_LIB, PROBE_UNITS)):
+        tmp = lib + ".tmp"
+        cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *(objs[u] for u in names)]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+        os.replace(tmp, lib)
     return LIB
 
 

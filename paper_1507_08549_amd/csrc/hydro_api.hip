@@ -679,34 +679,6 @@ int hydro_ls_redistance(hydro_ctx* c, double* S, double* dist, int64_t* npoints)
   return HYDRO_OK;
 }
 
-int hydro_probe_fma(hydro_ctx* c, int32_t iters, double* flops_per_s) {
-  if (!c || iters < 1 || !flops_per_s) return HYDRO_E_INVALID;
-  DeviceGuard dg(c->device);
-  if (!dg.ok) return HYDRO_E_DEVICE;
-  int cus = 0;
-  HY_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
-  const int blocks = 8 * (cus > 0 ? cus : 1);  // 8 workgroups of 4 waves per compute unit
-  hipEvent_t e0, e1;
-  HY_CHECK(hipEventCreate(&e0));
-  if (hipEventCreate(&e1) != hipSuccess) {
-    (void)hipEventDestroy(e0);
-    return HYDRO_E_DEVICE;
-  }
-  int rc = HYDRO_OK;
-  float ms = 0.0f;
-  if (hy::launch_fma_probe(c->sum_out, iters, blocks, c->stream) != hipSuccess ||  // warm-up
-      hipEventRecord(e0, c->stream) != hipSuccess ||
-      hy::launch_fma_probe(c->sum_out, iters, blocks, c->stream) != hipSuccess ||
-      hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-      hipEventElapsedTime(&ms, e0, e1) != hipSuccess || !(ms > 0.0f))
-    rc = HYDRO_E_DEVICE;
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  if (rc) return rc;
-  *flops_per_s = 2.0 * 8.0 * (double)iters * 256.0 * (double)blocks / (1e-3 * (double)ms);
-  return HYDRO_OK;
-}
-
 int hydro_sums(hydro_ctx* c, const double* U, double out_host[4]) {
   if (!c || !U || !out_host) return HYDRO_E_INVALID;
   DeviceGuard dg(c->device);

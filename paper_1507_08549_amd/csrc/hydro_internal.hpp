@@ -147,6 +147,5 @@ hipError_t launch_ls_front(const LsArgs& a, double* pts, hipStream_t s);
 hipError_t launch_ls_distance(const LsArgs& a, const double* pts, double* dist, hipStream_t s);
 hipError_t launch_ls_velocity(const LsArgs& a, const double* U, hipStream_t s);
 
-hipError_t launch_fma_probe(double* out, int iters, int blocks, hipStream_t s);
 
 }  // namespace hy

@@ -60,7 +60,7 @@ _lib = None
 ENTRY_POINTS = ("hydro_create", "hydro_destroy", "hydro_cfl", "hydro_step", "hydro_run",
                 "hydro_run_save", "hydro_rhs", "hydro_step_vjp", "hydro_step_save", "hydro_step_vjp_saved",
                 "hydro_poisson", "hydro_gravity", "hydro_ls_velocity", "hydro_ls_step", "hydro_ls_front",
-                "hydro_ls_redistance", "hydro_probe_fma", "hydro_sums", "hydro_check", "hydro_strerror")
+                "hydro_ls_redistance", "hydro_sums", "hydro_check", "hydro_strerror")
 
 
 def declared_entry_points(header: str = HEADER):
@@ -97,7 +97,6 @@ def load():
     lib.hydro_ls_step.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_double]
     lib.hydro_ls_front.argtypes = [vp, vp, vp, ctypes.c_int64, i64p]
     lib.hydro_ls_redistance.argtypes = [vp, vp, vp, i64p]
-    lib.hydro_probe_fma.argtypes = [vp, ctypes.c_int32, dp]
     lib.hydro_sums.argtypes = [vp, vp, dp]
     lib.hydro_check.argtypes = [vp]
     lib.hydro_strerror.argtypes = [ip]
@@ -361,12 +360,6 @@ class Solver:
                                            ctypes.byref(n))
         self._check(rc, "hydro_ls_redistance")
         return n.value
-
-    def probe_fma(self, iters=20000):
-        """Achievable FP64 fma rate of the device (flop/s)."""
-        r = ctypes.c_double()
-        self._check(self._lib.hydro_probe_fma(self._h, int(iters), ctypes.byref(r)), "hydro_probe_fma")
-        return r.value
 
     def sums(self, U):
         out = (ctypes.c_double * 4)()

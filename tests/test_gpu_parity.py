@@ -315,22 +315,3 @@ def test_fp32_bulk_sod_vs_oracle(torch, hydro, oracle_mod):
     assert t_gpu == 0.2 and abs(k - len(dts)) <= 1
     got = U.cpu().numpy()
     assert np.abs(got[0] - want[0]).sum() / np.abs(want[0]).sum() <= 1e-5
-
-
-def test_fma_probe_reports_a_plausible_rate(torch, hydro):
-    """The measurement aid behind the benchmark's achievable-peak figure: a
-    positive rate below the FP64 vector peak (78.6 TFLOP/s) by construction of
-    its instruction stream, and well above a naive host rate."""
-    prm, _ = inputs.kelvin_helmholtz(16)
-    s = hydro.Solver(prm)
-    try:
-        r = s.probe_fma(2000)
-    finally:
-        s.close()
-    assert 1e12 < r < 80e12, r
-    with pytest.raises(hydro.HydroError):
-        s2 = hydro.Solver(prm)
-        try:
-            s2.probe_fma(0)
-        finally:
-            s2.close()

@@ -136,6 +136,30 @@ int hydro_cfl(hydro_ctx* ctx, const double* U, double* dt_host);
 int hydro_step(hydro_ctx* ctx, double* U, double dt, const hydro_alpha* alpha_in,
                hydro_alpha* alpha_out);
 
+/* Largest grid (nx * ny cells) hydro_step_noalloc accepts. */
+#define HYDRO_NOALLOC_MAX_CELLS (1 << 20)
+
+/* hydro_step without a context, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): one SSP-RK3 step of U in place, exactly as hydro_step computes
+ * it (same kernels, same results bit for bit), allocating nothing.
+ *  params, gravity  as for hydro_create (params checked the same way; gravity
+ *             NULL or a device field [2][ny][nx]); nx * ny must not exceed
+ *             HYDRO_NOALLOC_MAX_CELLS (else INVALID, before any device call).
+ *  stream     a hipStream_t, or NULL for the null stream.
+ *  U, dt, alpha_in  as for hydro_step (alpha_in NULL: each stage computes its
+ *             LF speeds; else the given speeds are replayed).
+ *  unphysical NULL, or a device int32 that receives 1 if a stage produced
+ *             rho <= 0 or p <= 0, else 0 (there is no context whose flag
+ *             hydro_check could read).
+ * The stage states and reduction slots live in one device array of the
+ * library (64 MiB + 33 KiB per device, held until the process ends, set up on
+ * the first call on a device).  Every call on a device uses that array:
+ * calls on one device must not overlap in time (different streams race); each
+ * call clears what it needs.  Asynchronous. */
+int hydro_step_noalloc(const hydro_params* params, const double* gravity, void* stream, double* U,
+                       double dt, const hydro_alpha* alpha_in, int32_t* unphysical);
+
 /* Up to nsteps steps with the CFL time step computed on the device (no host
  * round trip between steps), each clamped so that t never passes t_end
  * (t_end <= 0: no clamp, exactly nsteps steps).

@@ -6,6 +6,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "hydro.h"
@@ -242,6 +243,56 @@ void free_ctx(hydro_ctx* c) {
   delete c;
 }
 
+// ---- the allocation-free step (hydro_step_noalloc)
+// Scratch of the step variant that allocates nothing: a control block
+// (reduction slots, flag), the partial maxima of the speed reduction and the
+// two stage states of a grid of at most HYDRO_NOALLOC_MAX_CELLS cells, in one
+// file-scope device array.  Each device holds its own copy from the first
+// launch of this library's code until the process ends.  In host code the
+// array's name is not a device address: hydro_step_noalloc looks the address
+// up once per device (hipGetSymbolAddress) and passes that pointer on.
+constexpr size_t kNaCtlBytes = (sizeof(hy::Ctl) + 255) / 256 * 256;
+constexpr size_t kNaPartialBytes = 256 * 4 * sizeof(double);
+constexpr size_t kNaStateBytes = 4 * (size_t)HYDRO_NOALLOC_MAX_CELLS * sizeof(double);
+constexpr size_t kNaScratchBytes = kNaCtlBytes + kNaPartialBytes + 2 * kNaStateBytes;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNaScratchBytes];
+
+namespace {
+std::mutex g_na_mutex;
+unsigned char* g_na_ptr[hy::MAX_DEVICES];  // device address of `scratch`, per device
+
+// Address of this device's scratch array (looked up on the first call on the device).
+int noalloc_scratch(int dev, unsigned char** out) {
+  if (dev < 0 || dev >= hy::MAX_DEVICES) return HYDRO_E_DEVICE;
+  std::lock_guard<std::mutex> lock(g_na_mutex);
+  if (!g_na_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return HYDRO_E_DEVICE;
+    g_na_ptr[dev] = static_cast<unsigned char*>(p);
+  }
+  *out = g_na_ptr[dev];
+  return HYDRO_OK;
+}
+
+// Start of a call: the error flag and the header of the control block cleared
+// (a kernel, not a memset, so that the call can be captured in a graph).
+__global__ void noalloc_begin_kernel(hy::Ctl* ctl) {
+  if (threadIdx.x == 0) {
+    ctl->t = 0.0;
+    ctl->dt = 0.0;
+    ctl->active = 1;
+    ctl->steps = 0;
+    ctl->flag = 0;
+  }
+}
+
+// End of a call: the flag (1: a stage produced rho <= 0 or p <= 0) to the caller.
+__global__ void noalloc_end_kernel(const hy::Ctl* ctl, int32_t* unphysical) {
+  if (threadIdx.x == 0) *unphysical = ctl->flag ? 1 : 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -324,6 +375,51 @@ int hydro_step_save(hydro_ctx* c, const double* U_in, double* U_out, double dt,
   DeviceGuard dg(c->device);
   if (!dg.ok) return HYDRO_E_DEVICE;
   return step_impl(c, U_in, U_out, dt, alpha_in, nullptr, U1_out, U2_out);
+}
+
+int hydro_step_noalloc(const hydro_params* params, const double* gravity, void* stream, double* U,
+                       double dt, const hydro_alpha* alpha_in, int32_t* unphysical) {
+  if (!U || !(dt >= 0.0)) return HYDRO_E_INVALID;
+  int rc = check_params(params);
+  if (rc) return rc;
+  if ((size_t)params->nx * (size_t)params->ny > (size_t)HYDRO_NOALLOC_MAX_CELLS) return HYDRO_E_INVALID;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return HYDRO_E_DEVICE;
+  unsigned char* base = nullptr;
+  if ((rc = noalloc_scratch(dev, &base))) return rc;
+  hy::Ctl* ctl = reinterpret_cast<hy::Ctl*>(base);
+  double* apart = reinterpret_cast<double*>(base + kNaCtlBytes);
+  double* S1 = reinterpret_cast<double*>(base + kNaCtlBytes + kNaPartialBytes);
+  double* S2 = reinterpret_cast<double*>(base + kNaCtlBytes + kNaPartialBytes + kNaStateBytes);
+  const hy::Geom g = make_geom(params, gravity);
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(noalloc_begin_kernel, dim3(1), dim3(64), 0, st, ctl);
+  HY_CHECK(hipGetLastError());
+  // the same launch sequence as hydro_step, on the scratch array's buffers
+  if (!alpha_in) HY_CHECK(hy::launch_alpha_reduce(g, U, ctl, 0, apart, st));
+  for (int s = 0; s < 3; ++s) {
+    hy::StageArgs a{};
+    a.g = g;
+    a.U0 = U;
+    a.V = s == 0 ? U : (s == 1 ? S1 : S2);
+    a.W = s == 0 ? S1 : (s == 1 ? S2 : U);
+    a.b = kStageWeight[s];
+    a.stage = s;
+    a.ctl = ctl;
+    a.dt_mode = 0;
+    a.dt_host = dt;
+    if (alpha_in) {
+      a.frozen = 1;
+      a.fax = alpha_in->ax[s];
+      a.fay = alpha_in->ay[s];
+    }
+    HY_CHECK(params->precision == HYDRO_FP64 ? hy::launch_stage_fp64(a, st) : hy::launch_stage_fp32(a, st));
+  }
+  if (unphysical) {
+    hipLaunchKernelGGL(noalloc_end_kernel, dim3(1), dim3(64), 0, st, ctl, unphysical);
+    HY_CHECK(hipGetLastError());
+  }
+  return HYDRO_OK;
 }
 
 int hydro_run(hydro_ctx* c, double* U, int32_t nsteps, double t_end, double* t_io, double* dt_rec,

@@ -59,6 +59,7 @@ _lib = None
 #: names of the entry points declared in include/hydro.h
 ENTRY_POINTS = ("hydro_create", "hydro_destroy", "hydro_cfl", "hydro_step", "hydro_run",
                 "hydro_run_save", "hydro_rhs", "hydro_step_vjp", "hydro_step_save", "hydro_step_vjp_saved",
+                "hydro_step_noalloc",
                 "hydro_poisson", "hydro_gravity", "hydro_ls_velocity", "hydro_ls_step", "hydro_ls_front",
                 "hydro_ls_redistance", "hydro_sums", "hydro_check", "hydro_strerror")
 
@@ -89,6 +90,8 @@ def load():
     lib.hydro_step_vjp.argtypes = [vp, vp, ctypes.c_double, ctypes.POINTER(Alpha), vp, vp]
     lib.hydro_step_save.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.POINTER(Alpha), vp, vp]
     lib.hydro_step_vjp_saved.argtypes = [vp, vp, vp, vp, ctypes.c_double, ctypes.POINTER(Alpha), vp, vp]
+    lib.hydro_step_noalloc.argtypes = [ctypes.POINTER(Params), vp, vp, vp, ctypes.c_double,
+                                       ctypes.POINTER(Alpha), vp]
     lib.hydro_poisson.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), dp]
     lib.hydro_gravity.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double, vp]
@@ -138,6 +141,37 @@ def _alpha_struct(alpha):
 
 def _alpha_array(s: Alpha):
     return np.array([[s.ax[k], s.ay[k]] for k in range(3)])
+
+
+#: largest grid hydro_step_noalloc accepts (nx * ny)
+NOALLOC_MAX_CELLS = 1 << 20
+
+
+def step_noalloc(params: dict, U, dt, alpha=None, gravity=None, precision=FP64, unphysical=None):
+    """hydro_step_noalloc: one SSP-RK3 step of U (float64 device tensor (4, ny, nx),
+    in place) with no context and no device allocation, on torch's current
+    stream.  gravity: None or a (2, ny, nx) float64 device tensor; unphysical:
+    None or a one-element int32 device tensor receiving 1 if a stage produced
+    rho <= 0 or p <= 0, else 0."""
+    import torch
+    lib = load()
+    nx, ny = int(params["nx"]), int(params["ny"])
+    for name, x, shape, dt_ in (("U", U, (4, ny, nx), torch.float64),
+                                ("gravity", gravity, (2, ny, nx), torch.float64),
+                                ("unphysical", unphysical, (1,), torch.int32)):
+        if x is None and name != "U":
+            continue
+        if (not isinstance(x, torch.Tensor) or x.dtype != dt_ or not x.is_cuda
+                or tuple(x.shape) != shape or not x.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous {dt_} device tensor of shape {shape}")
+    p = make_params(params, precision)
+    a = _alpha_struct(alpha)
+    rc = lib.hydro_step_noalloc(ctypes.byref(p), None if gravity is None else gravity.data_ptr(),
+                                torch.cuda.current_stream(U.device).cuda_stream, U.data_ptr(), float(dt),
+                                ctypes.byref(a) if a is not None else None,
+                                None if unphysical is None else unphysical.data_ptr())
+    if rc < 0:
+        raise HydroError(rc, "hydro_step_noalloc")
 
 
 class Solver:

@@ -27,11 +27,13 @@ BOUNDARY = {"hydro_create", "hydro_destroy", "hydro_cfl", "hydro_step", "hydro_s
 ADJOINT_ROLLOUT = {"hydro_run_save", "hydro_rhs", "hydro_step_save", "hydro_step_vjp_saved"}
 POTENTIAL = {"hydro_poisson", "hydro_gravity"}
 LEVEL_SET = {"hydro_ls_velocity", "hydro_ls_step", "hydro_ls_front", "hydro_ls_redistance"}
+# the step for callers that cannot allocate device memory
+NO_ALLOC = {"hydro_step_noalloc"}
 
 
 def test_header_declares_the_boundary():
     names = hydro.declared_entry_points()
-    assert set(names) == BOUNDARY | ADJOINT_ROLLOUT | POTENTIAL | LEVEL_SET
+    assert set(names) == BOUNDARY | ADJOINT_ROLLOUT | POTENTIAL | LEVEL_SET | NO_ALLOC
     assert sorted(hydro.ENTRY_POINTS) == names
     assert not any("probe" in n for n in names)
 
@@ -79,6 +81,21 @@ def test_null_arguments_rejected(lib):
     assert lib.hydro_step(None, None, 0.1, None, None) == hydro.HYDRO_E_INVALID
     assert lib.hydro_step_vjp(None, None, 0.1, None, None, None) == hydro.HYDRO_E_INVALID
     assert lib.hydro_check(None) == hydro.HYDRO_E_INVALID
+
+
+def test_noalloc_step_rejects_before_any_device_call(lib):
+    # a grid beyond the scratch array's capacity, a NULL state, a bad dt
+    prm, _ = inputs.kelvin_helmholtz(16)
+    big = hydro.make_params(dict(prm, nx=1025, ny=1024))
+    dummy = ctypes.c_void_p(16)
+    assert lib.hydro_step_noalloc(ctypes.byref(big), None, None, dummy, 0.1, None, None) == hydro.HYDRO_E_INVALID
+    ok = hydro.make_params(prm)
+    assert lib.hydro_step_noalloc(ctypes.byref(ok), None, None, None, 0.1, None, None) == hydro.HYDRO_E_INVALID
+    assert lib.hydro_step_noalloc(ctypes.byref(ok), None, None, dummy, -1.0, None, None) == hydro.HYDRO_E_INVALID
+    assert lib.hydro_step_noalloc(None, None, None, dummy, 0.1, None, None) == hydro.HYDRO_E_INVALID
+    bad = hydro.make_params(prm)
+    bad.gamma = 1.0
+    assert lib.hydro_step_noalloc(ctypes.byref(bad), None, None, dummy, 0.1, None, None) == hydro.HYDRO_E_INVALID
 
 
 def test_solver_refuses_to_run_without_gpu():

@@ -1,29 +1,33 @@
 #!/usr/bin/env python3
 """Throughput of the WENO5 / global-LF / SSP-RK3 hot path on one MI355X.
 
-Workload: the periodic shear layer (Kelvin-Helmholtz) on 512 x 512 cells,
-gamma = 5/3, CFL 0.5, seeded v_y noise; one "step" is one full SSP-RK3 step
-(three fused stage kernels: ghost fill, primitives, LF split, WENO5 in x and
-y, divergence and sources, stage combination, LF/CFL max-reduction) with the
-CFL time step computed on the device.  The state is resident in HBM before
-the timed region starts.
+Workload (the value): the n = 3 polytrope in cylindrical (r, z) geometry on
+1024 x 1024 cells, gamma = 4/3, CFL 0.5, fixed gravity field from the
+enclosed mass, atmosphere floors at rho = 1e-8, seeded 1e-3 density noise:
+its 1000 SSP-RK3 steps from the initial state.  One step is three fused stage
+kernels (ghost fill, primitives, LF split, WENO5 in x and y, divergence,
+gravity and geometric sources, stage combination, floors, LF/CFL
+max-reduction) with the CFL time step computed on the device.  The state and
+the gravity field are resident in HBM before the timed region starts.
 
-Reported (one JSON line): FP64 cell-updates/s (the value), the FP32-bulk
-form's rate and its relative L1 density error against the FP64 oracle, the
-roofline of the stage kernel, the oracle's own rate on the host cores, and the
+Reported (one JSON line): FP64 cell-updates/s (the value) with the final
+state's digest checked against the oracle's; the stage kernel's roofline
+(per-launch time from the difference of a K-step run and an empty run, both
+timed with HIP events on the solver's stream); the FP32-bulk form's rate and
+relative L1 density error against the oracle; the oracle's own rate on the
+host (one thread and all cores); and further legs: the periodic shear layer
+(512^2) with its own roofline, the other workloads at full length, the
 adjoint workload (sine-mode shear layer, 1024^2, 500 steps: backward/forward
-time ratio in FP64 and FP32 keeping every state, and with checkpoints every
-50 steps; central-difference check; FP32-vs-FP64 gradient error), and the potential solver on the polytrope
-density (1024^2, red-black over-relaxation to the relative change 1e-8), the
-level-set flame front (1025^2 corners: advection step and re-distancing), the
-characteristic-wise reconstruction on the same shear layer (rate, and a few
-steps against the oracle bit for bit), the step at 1024^2, 2048^2 and 4096^2
-(states beyond the last-level cache), and two achievable-peak probes (FP64 fma
-rate, device copy).
+ratio, FP32-bulk with checkpoints every 50 steps as the headline figure,
+central differences of all 64 mode amplitudes), the potential solver, the
+level-set flame front, the characteristic-wise reconstruction, the step at
+2048^2 and 4096^2, and two achievable-peak probes (FP64 fma rate, device
+copy).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -39,54 +43,68 @@ sys.path.insert(0, ROOT)
 # fma counted as 2 flops, a division or square root as 1): primitives and
 # split fluxes at the point for x and y (2 x 41), 8 WENO5 reconstructions
 # (8 x 66) plus the face sums (4) for the x face and the same for the y face
-# (2 x 532), divergence, sources, stage combination, output primitives and
-# the maxima (64).  See the design notes for the itemised count.
+# (2 x 532), divergence, uniform or field gravity, stage combination, output
+# primitives and the maxima (64).  See the design notes for the itemised count.
 FLOPS_PER_CELL_STAGE = 2 * 41 + 2 * (8 * 66 + 4) + 64
+# The polytrope adds the geometric sources of the cylindrical form (the cell's
+# primitives 12, its radius and 1/r 3, four source terms 12) and the pressure
+# floor's primitives of the new state (12).
+FLOPS_PER_CELL_STAGE_CYL_FLOORS = FLOPS_PER_CELL_STAGE + 27 + 12
 # Algorithmic HBM bytes of one step per cell: stage 1 reads U^n and writes U1;
-# stages 2 and 3 read U^n and their input and write their output (FP64 x 4).
+# stages 2 and 3 read U^n and their input and write their output (FP64 x 4);
+# with a gravity field each stage also reads (g_x, g_y) (2 x 8 B x 3).
 BYTES_PER_CELL_STEP = 32 * (2 + 3 + 3)
+BYTES_PER_CELL_STEP_FIELD = BYTES_PER_CELL_STEP + 3 * 16
 PEAK_FP64_VALU_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 # Algorithmic bytes of one red-black iteration per cell: rho once, the
 # potential read twice (as a cell of its colour and as a neighbour of the
-# other) and written once (FP64).
+# other) and written once (FP64): the count of a solver with one sweep per
+# launch.  The temporally blocked kernel moves less (measured below).
 POISSON_BYTES_PER_CELL_ITER = 8 * 4
-
-
-# HBM traffic of one stage-kernel launch on this workload, from two rocprofv3
-# --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by the factors a 256 MiB device
-# copy gives (x2.0 for FETCH, x1.0 for WRITE); the summary, with the commands,
-# is under profiles/.  It holds for the kernel sources with this digest only:
-# after any change to them the figure is reported as null until re-measured.
-STAGE_TRAFFIC = {
-    "sources": ["paper_1507_08549_amd/csrc/stage_kernel.hpp", "paper_1507_08549_amd/csrc/ieee.hpp",
-                "paper_1507_08549_amd/csrc/stage_fp64.hip", "paper_1507_08549_amd/csrc/hydro_internal.hpp"],
-    "sha256": "391f199656abe7698864bd73113063a5ae8ae9e81bd68b19ab537271b74a946f",
-    "n": 512,
-    "bytes_per_launch": (15.192 + 8.489) * 1e6,
-    # SQ_INSTS_VALU of the same launch (wavefront instructions), same digest
-    "valu_insts_per_launch": 6804486,
-}
 # VALU issue peak: 256 CUs x 4 SIMDs, one wave64 instruction per 4 cycles per
 # SIMD at 2.4 GHz (FP64 add, mul and fma issue at that rate).
 PEAK_VALU_WAVE_INSTS_PER_S = 256 * 4 * 2.4e9 / 4
 
+STAGE_SOURCES = ["paper_1507_08549_amd/csrc/stage_kernel.hpp", "paper_1507_08549_amd/csrc/ieee.hpp",
+                 "paper_1507_08549_amd/csrc/stage_fp64.hip", "paper_1507_08549_amd/csrc/hydro_internal.hpp"]
+# Counter figures of one FP64 stage-kernel launch per workload: HBM traffic
+# from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by the factors
+# a 256 MiB device copy gives (x2.0 for FETCH, x1.0 for WRITE), and
+# SQ_INSTS_VALU (wavefront instructions).  The summaries, with the commands,
+# are under profiles/.  They hold for the kernel sources with this digest only:
+# after any change to them the figures are reported as null until re-measured.
+STAGE_COUNTERS = {
+    "sha256": "391f199656abe7698864bd73113063a5ae8ae9e81bd68b19ab537271b74a946f",
+    "workloads": {
+        "kelvin_helmholtz_512x512": {"bytes_per_launch": (15.192 + 8.489) * 1e6,
+                                     "valu_insts_per_launch": 6804486},
+    },
+}
+# The potential solver's launch (4 iterations): measured HBM bytes and VALU
+# instructions (profiles/poisson_block_polytrope1024.md).
+POISSON_COUNTERS = {"sources": ["paper_1507_08549_amd/csrc/poisson.hip"],
+                    "sha256": "95ec086e5748981e710e82542427ad733d2f838d6e83560e48e50666d0a97e44", "iterations_per_launch": 4,
+                    "bytes_per_launch": 18.66e6 + 8.27e6, "valu_insts_per_launch": 9097838,
+                    "launch_us": 28.46}
 
-def stage_measured(n, key):
-    """A counter figure of the stage kernel (HBM bytes or VALU instructions per
-    launch), or None once its sources or the grid differ from the measured."""
-    import hashlib
+
+def sources_digest(files):
     h = hashlib.sha256()
-    for f in STAGE_TRAFFIC["sources"]:
+    for f in files:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    if h.hexdigest() != STAGE_TRAFFIC["sha256"] or n != STAGE_TRAFFIC["n"]:
+    return h.hexdigest()
+
+
+def stage_measured(workload, key):
+    """A counter figure of the FP64 stage kernel (HBM bytes or VALU instructions
+    per launch) on a workload, or None once its sources differ from the
+    measured ones or the workload was not measured."""
+    w = STAGE_COUNTERS["workloads"].get(workload)
+    if w is None or sources_digest(STAGE_SOURCES) != STAGE_COUNTERS["sha256"]:
         return None
-    return STAGE_TRAFFIC[key]
-
-
-def stage_traffic(n):
-    return stage_measured(n, "bytes_per_launch")
+    return w.get(key)
 
 
 def host_cpu():
@@ -120,6 +138,182 @@ def timed_run(torch, solver, U, steps):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return e0.elapsed_time(e1) / 1e3, wall
+
+
+def run_overhead(torch, solver, U, reps=7):
+    """Event time of a run of zero steps (the per-call set-up kernels and the
+    final read-back), median of reps: subtracted from a K-step run it leaves
+    the 3K stage launches."""
+    return float(np.median([timed_run(torch, solver, U, 0)[0] for _ in range(reps)]))
+
+
+def digest(a) -> str:
+    return hashlib.sha256(np.ascontiguousarray(a, dtype="<f8").tobytes()).hexdigest()
+
+
+def golden_state_digest(name, step):
+    """The oracle's state digest of a workload at a checkpoint (tests/golden), or None."""
+    path = os.path.join(ROOT, "tests", "golden", "full_length.json")
+    try:
+        w = json.load(open(path))["workloads"][name]
+    except (OSError, KeyError, ValueError):
+        return None
+    for cp in w["checkpoints"]:
+        if cp["step"] == step:
+            return cp["state"]
+    return None
+
+
+def stage_roofline(torch, solver, U0d, steps, ncell, flops_cell, bytes_cell_step, workload, kernel):
+    """Per-launch time of the FP64 stage kernel from K steps minus an empty run
+    (both event-timed on the solver's stream), and the roofline it gives."""
+    U = U0d.clone()
+    t_k, _ = timed_run(torch, solver, U, steps)
+    t_0 = run_overhead(torch, solver, U)
+    stage_s = (t_k - t_0) / (3 * steps)
+    achieved = flops_cell * ncell / stage_s / 1e12
+    insts = stage_measured(workload, "valu_insts_per_launch")
+    issue = None if insts is None else {
+        "valu_wave_insts_per_launch": insts, "achieved_per_s": insts / stage_s,
+        "peak_per_s": PEAK_VALU_WAVE_INSTS_PER_S, "frac": insts / stage_s / PEAK_VALU_WAVE_INSTS_PER_S}
+    hbm = bytes_cell_step * ncell / 3 / stage_s / 1e9
+    return {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_VALU_TFLOPS,
+            "traffic": stage_measured(workload, "bytes_per_launch"), "traffic_unit": "bytes per launch",
+            "algorithmic_flops_per_launch": flops_cell * ncell,
+            "algorithmic_bytes_per_launch": bytes_cell_step * ncell / 3,
+            "kernel": kernel, "avg_launch_us": stage_s * 1e6,
+            "timing": f"({steps} steps {t_k * 1e3:.3f} ms - empty run {t_0 * 1e3:.3f} ms) / {3 * steps} launches",
+            "hbm_gbs_algorithmic": hbm, "hbm_frac": hbm / PEAK_HBM_GBS, "issue": issue}
+
+
+def headline_leg(torch, hydro, inputs, args):
+    """The polytrope's 1000 steps from its initial state, FP64 (timed K steps,
+    repeated from the same start), the stage roofline, FP32-bulk beside it."""
+    name = "polytrope_1024"
+    prm, U0, grav = inputs.polytrope(1024)
+    ncell = prm["nx"] * prm["ny"]
+    g = torch.tensor(grav, dtype=torch.float64, device="cuda")
+    U0d = torch.tensor(U0, dtype=torch.float64, device="cuda")
+    s64 = hydro.Solver(prm, gravity=g, precision=hydro.FP64)
+    U = U0d.clone()
+    s64.run(U, args.warmup)  # warm-up on a copy: clocks, code objects
+    runs = []
+    final = None
+    for r in range(max(args.repeats, 1)):
+        U = U0d.clone()
+        t, wall = timed_run(torch, s64, U, args.steps)
+        runs.append(ncell * args.steps / t)
+        if r == 0:
+            t64, wall64 = t, wall
+            final = U.cpu().numpy()
+    v64 = runs[0]
+    log(f"fp64: {args.steps} steps of the 1024^2 polytrope in {t64 * 1e3:.2f} ms (wall {wall64 * 1e3:.2f}) "
+        f"-> {v64:.4e} cell-updates/s; over {len(runs)} runs median {np.median(runs):.4e}")
+    want = golden_state_digest(name, args.steps)
+    check = None if want is None else bool(digest(final) == want)
+    roof = stage_roofline(torch, s64, U0d, args.steps, ncell, FLOPS_PER_CELL_STAGE_CYL_FLOORS,
+                          BYTES_PER_CELL_STEP_FIELD, "polytrope_1024x1024",
+                          "stage_kernel<double,16,16,true,false>")
+    log(f"stage kernel: {roof['avg_launch_us']:.2f} us per launch, {roof['achieved']:.1f} TFLOP/s "
+        f"({roof['frac']:.3f} of the FP64 peak)")
+    fp32 = None
+    if not args.only_fp64:
+        s32 = hydro.Solver(prm, gravity=g, precision=hydro.FP32_BULK)
+        U32 = U0d.clone()
+        s32.run(U32, args.warmup)
+        U32 = U0d.clone()
+        t32, _ = timed_run(torch, s32, U32, args.steps)
+        fp32 = {"value": ncell * args.steps / t32, "ms_per_step": t32 * 1e3 / args.steps,
+                "l1_rel_density_err_vs_oracle": float(np.abs(U32[0].cpu().numpy() - final[0]).sum()
+                                                      / np.abs(final[0]).sum()) if check else None,
+                "err_steps": args.steps,
+                "err_reference": "the FP64 state after the same steps, whose digest equals the oracle's"}
+        log(f"fp32-bulk: {fp32['value']:.4e} cell-updates/s, L1 rel density error "
+            f"{fp32['l1_rel_density_err_vs_oracle']}")
+        s32.close()
+    res = {"value": v64, "t64": t64, "runs": runs, "roofline": roof, "fp32": fp32,
+           "fp64_digest_equals_oracle": check, "solver": s64, "prm": prm, "U0": U0, "grav": grav}
+    return res
+
+
+def cpu_leg(torch, hydro, head, steps_all, steps_one):
+    """The oracle on the host: the headline workload's first steps on all the
+    cores OpenMP is given and on one, each state compared bit for bit with the
+    GPU's after as many steps."""
+    import oracle
+    prm, U0, grav = head["prm"], head["U0"], head["grav"]
+    ncell = prm["nx"] * prm["ny"]
+    o = oracle.Oracle(prm, gravity=grav)
+    keep = oracle.threads()
+    out = {}
+    try:
+        for key, nthreads, steps in (("all", keep, steps_all), ("one", 1, steps_one)):
+            if steps <= 0:
+                continue
+            used = oracle.set_threads(nthreads)
+            c0 = time.perf_counter()
+            ref, _, _, _ = o.run(U0, steps)
+            ct = time.perf_counter() - c0
+            U = torch.tensor(U0, dtype=torch.float64, device="cuda")
+            head["solver"].run(U, steps)
+            out[key] = {"value": ncell * steps / ct, "threads": used, "steps": steps, "seconds": ct,
+                        "fp64_bitwise_equal": bool(np.array_equal(U.cpu().numpy(), ref))}
+            log(f"oracle ({used} threads): {out[key]['value']:.4e} cell-updates/s over {steps} steps "
+                f"({ct:.1f} s), GPU bitwise {out[key]['fp64_bitwise_equal']}")
+    finally:
+        oracle.set_threads(keep)
+    if "all" not in out:
+        return None
+    a = out["all"]
+    cpu = {"value": a["value"], "unit": "cell-updates/s", "cores": a["threads"], "kind": "oracle",
+           "sample": f"the first {a['steps']} SSP-RK3 steps of the same 1024^2 polytrope, C oracle with "
+                     f"OpenMP over rows, columns and cells ({a['threads']} threads, {a['seconds']:.1f} s)",
+           "fp64_bitwise_equal": a["fp64_bitwise_equal"], "host": host_cpu()}
+    if "one" in out:
+        o1 = out["one"]
+        cpu["one_core"] = {"value": o1["value"], "cores": 1,
+                           "sample": f"the first {o1['steps']} steps, one thread ({o1['seconds']:.1f} s)",
+                           "fp64_bitwise_equal": o1["fp64_bitwise_equal"]}
+    return cpu
+
+
+def shear_layer_leg(torch, hydro, inputs, n, steps, warmup, cpu_steps, only_fp64):
+    """The periodic shear layer (n^2, the 2000-step workload's grid): FP64 rate
+    and stage roofline, FP32-bulk rate, and its error against the oracle after
+    cpu_steps steps."""
+    prm, U0 = inputs.kelvin_helmholtz(n, seed=2)
+    ncell = n * n
+    s64 = hydro.Solver(prm)
+    U0d = torch.tensor(U0, dtype=torch.float64, device="cuda")
+    U = U0d.clone()
+    s64.run(U, warmup)
+    U = U0d.clone()
+    t64, _ = timed_run(torch, s64, U, steps)
+    res = {"workload": f"kelvin_helmholtz_{n}x{n}", "steps": steps, "value": ncell * steps / t64,
+           "ms_per_step": t64 * 1e3 / steps}
+    res["roofline"] = stage_roofline(torch, s64, U0d, steps, ncell, FLOPS_PER_CELL_STAGE, BYTES_PER_CELL_STEP,
+                                     f"kelvin_helmholtz_{n}x{n}", "stage_kernel<double,16,16,true,false>")
+    log(f"shear layer {n}^2: {res['value']:.4e} cell-updates/s, {res['roofline']['avg_launch_us']:.2f} us per "
+        f"launch ({res['roofline']['frac']:.3f} of the FP64 peak)")
+    if not only_fp64:
+        s32 = hydro.Solver(prm, precision=hydro.FP32_BULK)
+        U32 = U0d.clone()
+        s32.run(U32, warmup)
+        U32 = U0d.clone()
+        t32, _ = timed_run(torch, s32, U32, steps)
+        res["fp32_value"] = ncell * steps / t32
+        if cpu_steps > 0:
+            import oracle
+            ref, _, _, _ = oracle.Oracle(prm).run(U0, cpu_steps)
+            U32 = U0d.clone()
+            s32.run(U32, cpu_steps)
+            res["fp32_l1_rel_density_err_vs_oracle"] = float(np.abs(U32[0].cpu().numpy() - ref[0]).sum()
+                                                             / np.abs(ref[0]).sum())
+            res["fp32_err_steps"] = cpu_steps
+        s32.close()
+    s64.close()
+    return res
 
 
 def adjoint_leg(torch, hydro, inputs, n, steps, ckpt, precision, a_np, sched=None):
@@ -172,6 +366,43 @@ def fd_check(torch, inputs, s, a_np, sched, comps, h=1e-7):
         e[k] = h
         out.append((J_of(a_np + e) - J_of(a_np - e)) / (2 * h))
     return np.array(out)
+
+
+def adjoint_block(torch, hydro, inputs, args):
+    """The adjoint workload in its stated form (FP32-bulk, checkpoints every
+    ckpt steps: the headline ratio) and the other three forms; central
+    differences of the FP64 gradient over every mode amplitude."""
+    a_np = inputs.kh_sine_amplitudes()
+    n, steps, ck = args.adj_n, args.adj_steps, args.adj_ckpt
+    s64a, J64, g64, tf64, tb64, sched = adjoint_leg(torch, hydro, inputs, n, steps, None, hydro.FP64, a_np)
+    _, J32, g32, tf32, tb32, _ = adjoint_leg(torch, hydro, inputs, n, steps, None, hydro.FP32_BULK, a_np, sched)
+    _, _, g64c, tf64c, tb64c, _ = adjoint_leg(torch, hydro, inputs, n, steps, ck, hydro.FP64, a_np, sched)
+    _, _, g32c, tf32c, tb32c, _ = adjoint_leg(torch, hydro, inputs, n, steps, ck, hydro.FP32_BULK, a_np, sched)
+    comps = list(range(len(a_np))) if args.fd_all else [0, 17, 63]
+    c0 = time.perf_counter()
+    fd = fd_check(torch, inputs, s64a, a_np, sched, comps)
+    fd_s = time.perf_counter() - c0
+    rel = np.abs(fd - g64[comps]) / np.abs(g64[comps])
+    adj = {"workload": f"kh_sine_{n}x{n}_{steps}steps",
+           "ratio": tb32c / tf32c,
+           "ratio_form": f"FP32-bulk, checkpoints every {ck} steps (backward incl. segment replay / forward)",
+           "J": J64,
+           "fwd_ms_fp32_ckpt": tf32c * 1e3, "bwd_ms_fp32_ckpt": tb32c * 1e3,
+           "ratio_fp64_ckpt": tb64c / tf64c, "fwd_ms_fp64_ckpt": tf64c * 1e3, "bwd_ms_fp64_ckpt": tb64c * 1e3,
+           "ratio_fp64_all_states": tb64 / tf64, "ratio_fp32_all_states": tb32 / tf32,
+           "states_kept_gb": 3 * steps * 32 * n * n / 1e9, "ckpt_every": ck,
+           "ckpt_grad_bitwise_equal_fp64": bool(np.array_equal(g64c, g64)),
+           "ckpt_grad_bitwise_equal_fp32": bool(np.array_equal(g32c, g32)),
+           "fd_components": len(comps), "fd_h": 1e-7, "fd_seconds": fd_s,
+           "fd_rel_err_max": float(rel.max()), "fd_rel_err_median": float(np.median(rel)),
+           "fd_rel_err_worst_component": int(comps[int(np.argmax(rel))]),
+           "grad_rel_err_fp32_vs_fp64": float(np.linalg.norm(g32 - g64) / np.linalg.norm(g64)),
+           "grad_rel_err_fp32_vs_fp64_max_component": float(np.max(np.abs(g32 - g64) / np.abs(g64)))}
+    log(f"adjoint: FP32 checkpointed ratio {adj['ratio']:.2f} (fwd {tf32c * 1e3:.1f} ms, bwd {tb32c * 1e3:.1f} ms); "
+        f"FP64 checkpointed {adj['ratio_fp64_ckpt']:.2f}; all states {adj['ratio_fp64_all_states']:.2f} / "
+        f"{adj['ratio_fp32_all_states']:.2f}; FD over {len(comps)} amplitudes: max rel err "
+        f"{adj['fd_rel_err_max']:.2e} ({fd_s:.1f} s); fp32 grad rel err {adj['grad_rel_err_fp32_vs_fp64']:.2e}")
+    return adj
 
 
 PROBE_LIB = os.path.join(ROOT, "paper_1507_08549_amd", "libhydro_probe.so")
@@ -274,38 +505,33 @@ def charwise_leg(torch, hydro, inputs, n, steps, cpu_steps):
 
 
 def configs_leg(torch, hydro, inputs):
-    """The other workloads at their full lengths, FP64 and FP32-bulk: rates, the
-    FP32 form's relative L1 density error against the FP64 path (which matches
-    the oracle bit for bit on every prefix the tests check), and the
-    polytrope's equilibrium drift (max |v| / c_center and the L1 density change
-    after 1000 steps; no exact value exists, the scheme is not well balanced)."""
-    cases = [("kelvin_helmholtz_512x512_2000steps", lambda: inputs.kelvin_helmholtz(512, seed=2) + (None,), 2000),
-             ("rayleigh_taylor_256x1024_5000steps", lambda: inputs.rayleigh_taylor() + (None,), 5000),
-             ("polytrope_1024x1024_1000steps", lambda: inputs.polytrope(1024), 1000)]
+    """The shear layer (2000 steps) and the heavy-over-light layer (5000 steps)
+    at full length, FP64 and FP32-bulk: rates, the FP64 final state's digest
+    against the oracle's, and the FP32 form's relative L1 density error against
+    that state (the oracle's when the digests agree)."""
+    cases = [("shear_layer_512", "kelvin_helmholtz_512x512_2000steps",
+              lambda: inputs.kelvin_helmholtz(512, seed=2), 2000),
+             ("heavy_over_light_256x1024", "rayleigh_taylor_256x1024_5000steps",
+              lambda: inputs.rayleigh_taylor(), 5000)]
     out = []
-    for name, make, steps in cases:
-        prm, U0, grav = make()
-        g = None if grav is None else torch.tensor(grav, dtype=torch.float64, device="cuda")
+    for key, name, make, steps in cases:
+        prm, U0 = make()
         res = {"workload": name}
         fin = {}
-        for prec, key in ((hydro.FP64, "fp64"), (hydro.FP32_BULK, "fp32")):
-            s = hydro.Solver(prm, gravity=g, precision=prec)
+        for prec, k in ((hydro.FP64, "fp64"), (hydro.FP32_BULK, "fp32")):
+            s = hydro.Solver(prm, precision=prec)
             U = torch.tensor(U0, dtype=torch.float64, device="cuda")
             t, _ = timed_run(torch, s, U, steps)
-            res[f"{key}_cell_updates_per_s"] = prm["nx"] * prm["ny"] * steps / t
-            fin[key] = U
+            res[f"{k}_cell_updates_per_s"] = prm["nx"] * prm["ny"] * steps / t
+            fin[k] = U.cpu().numpy()
             s.close()
-        d = (fin["fp32"][0] - fin["fp64"][0]).abs().sum() / fin["fp64"][0].abs().sum()
-        res["fp32_l1_rel_density_err_vs_fp64"] = float(d)
-        if grav is not None:
-            U = fin["fp64"]
-            rho0 = torch.tensor(U0[0], dtype=torch.float64, device="cuda")
-            vmag = torch.sqrt(U[1] ** 2 + U[2] ** 2) / U[0]
-            dense = rho0 > 1e-3
-            res["drift_l1_rel_density"] = float((U[0] - rho0).abs().sum() / rho0.abs().sum())
-            res["drift_max_speed_over_c_center_dense"] = float(vmag[dense].max() / math.sqrt(4.0 / 3.0))
+        want = golden_state_digest(key, steps)
+        res["fp64_digest_equals_oracle"] = None if want is None else bool(digest(fin["fp64"]) == want)
+        d = np.abs(fin["fp32"][0] - fin["fp64"][0]).sum() / np.abs(fin["fp64"][0]).sum()
+        res["fp32_l1_rel_density_err_vs_oracle" if res["fp64_digest_equals_oracle"]
+            else "fp32_l1_rel_density_err_vs_fp64"] = float(d)
         log(f"config {name}: fp64 {res['fp64_cell_updates_per_s']:.3e}, fp32 {res['fp32_cell_updates_per_s']:.3e} "
-            f"cell-updates/s, fp32 L1 err {res['fp32_l1_rel_density_err_vs_fp64']:.2e}")
+            f"cell-updates/s, oracle digest {res['fp64_digest_equals_oracle']}, fp32 L1 err {d:.2e}")
         out.append(res)
     return out
 
@@ -313,7 +539,6 @@ def configs_leg(torch, hydro, inputs):
 def poisson_leg(torch, hydro, inputs, n, cpu_iters):
     """Potential of the n = 3 polytrope's density from a zero start to the
     relative change 1e-8 with the near-optimal over-relaxation factor."""
-    import math
     prm, U0, _ = inputs.polytrope(n)
     L = prm["xhi"]
     rho_np = np.ascontiguousarray(U0[0])
@@ -338,14 +563,21 @@ def poisson_leg(torch, hydro, inputs, n, cpu_iters):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     t = e0.elapsed_time(e1) / 1e3
+    us_it = t * 1e6 / iters
     out = {"workload": f"polytrope_density_{n}x{n}_zero_start_tol1e-8", "omega": omega,
            "iterations": iters, "last_change": change, "ms": t * 1e3, "wall_ms": wall * 1e3,
-           "cell_iterations_per_s": n * n * iters / t,
-           "us_per_iteration": t * 1e6 / iters,
-           "hbm_gbs_algorithmic": POISSON_BYTES_PER_CELL_ITER * n * n * iters / t / 1e9}
-    out["hbm_frac"] = out["hbm_gbs_algorithmic"] / PEAK_HBM_GBS
-    log(f"poisson: {iters} iterations in {t * 1e3:.1f} ms ({out['us_per_iteration']:.2f} us/iteration, "
-        f"{out['hbm_gbs_algorithmic']:.0f} GB/s algorithmic)")
+           "cell_iterations_per_s": n * n * iters / t, "us_per_iteration": us_it,
+           "hbm_gbs_single_sweep_count": POISSON_BYTES_PER_CELL_ITER * n * n * iters / t / 1e9}
+    pc = POISSON_COUNTERS
+    if n == 1024 and sources_digest(pc["sources"]) == pc["sha256"]:
+        k = pc["iterations_per_launch"]
+        out["measured"] = {
+            "hbm_bytes_per_cell_iteration": pc["bytes_per_launch"] / k / (n * n),
+            "hbm_gbs_during_launch": pc["bytes_per_launch"] / (pc["launch_us"] * 1e-6) / 1e9,
+            "issue_frac": pc["valu_insts_per_launch"] / (pc["launch_us"] * 1e-6) / PEAK_VALU_WAVE_INSTS_PER_S,
+            "bound": "issue and LDS latency (temporal blocking keeps HBM traffic low)",
+            "counters_launch_us": pc["launch_us"]}
+    log(f"poisson: {iters} iterations in {t * 1e3:.1f} ms ({us_it:.2f} us/iteration)")
     if cpu_iters > 0:
         import oracle
         c0 = time.perf_counter()
@@ -408,34 +640,41 @@ def levelset_leg(torch, hydro, inputs, n, steps, cpu):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--n", type=int, default=512, help="grid size (n x n)")
+    ap.add_argument("--steps", type=int, default=1000,
+                    help="timed steps of the polytrope (its full length: 1000)")
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--repeats", type=int, default=5,
-                    help="timed runs of K steps (the first is the value; all give the median)")
-    ap.add_argument("--cpu-steps", type=int, default=100,
-                    help="oracle steps timed for the CPU baseline (0: skip)")
-    ap.add_argument("--only-fp64", action="store_true", help="skip the FP32-bulk leg")
+                    help="timed runs of K steps from the initial state (the first is the value)")
+    ap.add_argument("--cpu-steps", type=int, default=40,
+                    help="oracle steps of the polytrope timed on all cores (0: skip every CPU leg)")
+    ap.add_argument("--cpu-steps-one", type=int, default=10, help="oracle steps timed on one thread")
+    ap.add_argument("--only-fp64", action="store_true", help="skip the FP32-bulk legs")
+    ap.add_argument("--only-headline", action="store_true", help="the polytrope only (for profiling)")
+    ap.add_argument("--kh-n", type=int, default=512, help="shear-layer leg grid (n x n; 0: skip)")
+    ap.add_argument("--kh-steps", type=int, default=2000)
+    ap.add_argument("--kh-cpu-steps", type=int, default=100,
+                    help="oracle steps for the shear layer's FP32 error")
     ap.add_argument("--char-steps", type=int, default=400,
                     help="steps of the characteristic-reconstruction leg (0: skip)")
     ap.add_argument("--char-cpu-steps", type=int, default=3,
                     help="oracle steps of that leg compared bit for bit")
     ap.add_argument("--adj-n", type=int, default=1024, help="adjoint workload grid (n x n; 0: skip)")
     ap.add_argument("--adj-steps", type=int, default=500)
-    ap.add_argument("--adj-ckpt", type=int, default=50,
-                    help="checkpoint interval of the checkpointed adjoint figure (the headline keeps all states)")
+    ap.add_argument("--adj-ckpt", type=int, default=50, help="checkpoint interval of the adjoint")
+    ap.add_argument("--fd-all", type=int, default=1,
+                    help="central differences over all 64 amplitudes (0: three of them)")
     ap.add_argument("--poisson-n", type=int, default=1024,
                     help="potential-solver workload grid (n x n; 0: skip)")
     ap.add_argument("--poisson-cpu-iters", type=int, default=200)
     ap.add_argument("--ls-n", type=int, default=1024, help="level-set workload cells per side (0: skip)")
     ap.add_argument("--ls-steps", type=int, default=20)
-    ap.add_argument("--sweep", type=str, default="1024,2048,4096",
+    ap.add_argument("--sweep", type=str, default="2048,4096",
                     help="grid sizes of the out-of-cache sweep (comma separated; empty: skip)")
     ap.add_argument("--sweep-steps", type=int, default=200)
     ap.add_argument("--no-probes", action="store_true", help="skip the fma-rate and copy probes")
     ap.add_argument("--no-configs", action="store_true",
-                    help="skip the full-length runs of the other workloads (shear layer 2000 steps, "
-                         "heavy-over-light layer 5000, polytrope 1000)")
+                    help="skip the full-length runs of the shear layer (2000 steps) and the "
+                         "heavy-over-light layer (5000)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB three times (a known-size "
                          "kernel for calibrating the profiler's HBM byte counters)")
@@ -454,154 +693,66 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU", file=sys.stderr)
         sys.exit(1)
-    n = args.n
-    prm, U0 = inputs.kelvin_helmholtz(n, seed=2)
-    ncell = n * n
+    if args.only_headline:
+        args.kh_n = args.char_steps = args.adj_n = args.poisson_n = args.ls_n = 0
+        args.sweep = ""
+        args.no_probes = args.no_configs = True
+        args.cpu_steps = 0
 
-    # ---- FP64 (the value)
-    s64 = hydro.Solver(prm, precision=hydro.FP64)
-    U = torch.tensor(U0, dtype=torch.float64, device="cuda")
-    s64.run(U, args.warmup)
-    t64, wall64 = timed_run(torch, s64, U, args.steps)
-    v64 = ncell * args.steps / t64
-    log(f"fp64: {args.steps} steps in {t64 * 1e3:.2f} ms (wall {wall64 * 1e3:.2f}) -> {v64:.4e} cell-updates/s")
-    # the same K steps timed again (the flow continues), for the spread over runs
-    reps = [v64]
-    for _ in range(max(args.repeats, 1) - 1):
-        t, _ = timed_run(torch, s64, U, args.steps)
-        reps.append(ncell * args.steps / t)
-    repeats = {"runs": len(reps), "median": float(np.median(reps)), "min": min(reps), "max": max(reps)}
-    if len(reps) > 1:
-        log(f"fp64 over {len(reps)} runs of {args.steps} steps: median {repeats['median']:.4e}, "
-            f"min {repeats['min']:.4e}, max {repeats['max']:.4e}")
-
-    # stage-kernel average duration: 3 stage launches per step (plus three tiny
-    # set-up kernels per call, included, so the estimate is conservative)
-    stage_s = t64 / (3 * args.steps)
-    # the binding roof as instruction issue: measured VALU instructions per
-    # launch over the launch time, against the issue peak
-    insts = stage_measured(n, "valu_insts_per_launch")
-    issue = None if insts is None else {
-        "valu_wave_insts_per_launch": insts, "achieved_per_s": insts / stage_s,
-        "peak_per_s": PEAK_VALU_WAVE_INSTS_PER_S, "frac": insts / stage_s / PEAK_VALU_WAVE_INSTS_PER_S}
-    flops_launch = FLOPS_PER_CELL_STAGE * ncell
-    achieved_tf = flops_launch / stage_s / 1e12
-    hbm_gbs = BYTES_PER_CELL_STEP * ncell / 3 / stage_s / 1e9
-
-    # ---- FP32 bulk
-    fp32 = None
-    if not args.only_fp64:
-        s32 = hydro.Solver(prm, precision=hydro.FP32_BULK)
-        U32 = torch.tensor(U0, dtype=torch.float64, device="cuda")
-        s32.run(U32, args.warmup)
-        t32, _ = timed_run(torch, s32, U32, args.steps)
-        fp32 = {"value": ncell * args.steps / t32, "ms_per_step": t32 * 1e3 / args.steps}
-        log(f"fp32-bulk: {fp32['value']:.4e} cell-updates/s")
-
-    # ---- oracle on the host (bounded sample), and the errors it pins
+    head = headline_leg(torch, hydro, inputs, args)
     cpu = None
     if args.cpu_steps > 0:
-        import oracle
-        o = oracle.Oracle(prm)
-        c0 = time.perf_counter()
-        ref, _, _, _ = o.run(U0, args.cpu_steps)
-        ct = time.perf_counter() - c0
-        cpu = {"value": ncell * args.cpu_steps / ct, "unit": "cell-updates/s", "cores": 1,
-               "kind": "oracle",
-               "sample": f"{args.cpu_steps} SSP-RK3 steps of the same {n}x{n} shear layer, "
-                         f"single-threaded C oracle, {ct:.1f} s"}
-        cpu["host"] = host_cpu()
-        log(f"oracle: {cpu['value']:.4e} cell-updates/s ({ct:.1f} s)")
-        Uc = torch.tensor(U0, dtype=torch.float64, device="cuda")
-        s64.run(Uc, args.cpu_steps)
-        g64 = Uc.cpu().numpy()
-        cpu["fp64_bitwise_equal"] = bool(np.array_equal(g64, ref))
-        if fp32 is not None:
-            U32 = torch.tensor(U0, dtype=torch.float64, device="cuda")
-            s32.run(U32, args.cpu_steps)
-            g32 = U32.cpu().numpy()
-            fp32["l1_rel_density_err_vs_oracle"] = float(np.abs(g32[0] - ref[0]).sum() / np.abs(ref[0]).sum())
-            fp32["err_steps"] = args.cpu_steps
+        cpu = cpu_leg(torch, hydro, head, args.cpu_steps, args.cpu_steps_one)
+    head["solver"].close()
 
-    # ---- adjoint: sine-mode shear layer, gradient of the final y-kinetic energy
-    adj = None
-    if args.adj_n > 0:
-        a_np = inputs.kh_sine_amplitudes()
-        # headline: every state kept (3 x 500 states of 32 MiB at 1024^2), no replay
-        s64a, J64, g64, tf64, tb64, sched = adjoint_leg(torch, hydro, inputs, args.adj_n, args.adj_steps,
-                                                       None, hydro.FP64, a_np)
-        _, J32, g32, tf32, tb32, _ = adjoint_leg(torch, hydro, inputs, args.adj_n, args.adj_steps,
-                                                 None, hydro.FP32_BULK, a_np, sched)
-        # the same gradient with checkpoints (stage states recomputed per segment)
-        _, _, g64c, tf64c, tb64c, _ = adjoint_leg(torch, hydro, inputs, args.adj_n, args.adj_steps,
-                                                  args.adj_ckpt, hydro.FP64, a_np, sched)
-        _, _, _, tf32c, tb32c, _ = adjoint_leg(torch, hydro, inputs, args.adj_n, args.adj_steps,
-                                               args.adj_ckpt, hydro.FP32_BULK, a_np, sched)
-        comps = [0, 17, 63]
-        fd = fd_check(torch, inputs, s64a, a_np, sched, comps)
-        fd_err = float(np.max(np.abs(fd - g64[comps]) / np.abs(g64).max()))
-        adj = {"workload": f"kh_sine_{args.adj_n}x{args.adj_n}_{args.adj_steps}steps",
-               "J": J64,
-               "states_kept_gb": 3 * args.adj_steps * 32 * args.adj_n * args.adj_n / 1e9,
-               "fwd_ms_fp64": tf64 * 1e3, "bwd_ms_fp64": tb64 * 1e3, "ratio_fp64": tb64 / tf64,
-               "fwd_ms_fp32": tf32 * 1e3, "bwd_ms_fp32": tb32 * 1e3, "ratio_fp32": tb32 / tf32,
-               "ckpt_every": args.adj_ckpt,
-               "ratio_fp64_ckpt": tb64c / tf64c, "ratio_fp32_ckpt": tb32c / tf32c,
-               "ckpt_grad_bitwise_equal": bool(np.array_equal(g64c, g64)),
-               "fd_components": comps, "fd_rel_err_fp64": fd_err,
-               "grad_rel_err_fp32_vs_fp64": float(np.linalg.norm(g32 - g64) / np.linalg.norm(g64))}
-        log(f"adjoint: fp64 ratio {adj['ratio_fp64']:.2f} (fwd {tf64 * 1e3:.1f} ms, bwd {tb64 * 1e3:.1f} ms), "
-            f"fp32 ratio {adj['ratio_fp32']:.2f}; checkpointed every {args.adj_ckpt}: "
-            f"{adj['ratio_fp64_ckpt']:.2f} / {adj['ratio_fp32_ckpt']:.2f}; FD rel err {fd_err:.2e}, "
-            f"fp32 grad rel err {adj['grad_rel_err_fp32_vs_fp64']:.2e}")
-
+    kh = None
+    if args.kh_n > 0:
+        kh = shear_layer_leg(torch, hydro, inputs, args.kh_n, args.kh_steps, 200,
+                             args.kh_cpu_steps if args.cpu_steps > 0 else 0, args.only_fp64)
+    adj = None if args.adj_n <= 0 else adjoint_block(torch, hydro, inputs, args)
     prb = None if args.no_probes else probes(torch)
     sweep = None
     if args.sweep:
         sweep = sweep_leg(torch, hydro, inputs, [int(v) for v in args.sweep.split(",") if v], args.sweep_steps)
-
     cfgs = None if args.no_configs else configs_leg(torch, hydro, inputs)
-
     pois = None
     if args.poisson_n > 0:
         pois = poisson_leg(torch, hydro, inputs, args.poisson_n,
                            args.poisson_cpu_iters if args.cpu_steps > 0 else 0)
-
     chw = None
     if args.char_steps > 0:
-        chw = charwise_leg(torch, hydro, inputs, n, args.char_steps,
+        chw = charwise_leg(torch, hydro, inputs, 512, args.char_steps,
                            args.char_cpu_steps if args.cpu_steps > 0 else 0)
-
     lset = None
     if args.ls_n > 0:
         lset = levelset_leg(torch, hydro, inputs, args.ls_n, args.ls_steps, args.cpu_steps > 0)
 
+    runs = head["runs"]
     out = {
         "metric": "cell-updates/sec per RK3 step FP64 vs FP32 at stated L1 err; adjoint/fwd ratio",
-        "value": v64,
+        "value": head["value"],
         "unit": "cell-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": t64 * 1e3 / args.steps,
+        "ms_per_step": head["t64"] * 1e3 / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"kelvin_helmholtz_{n}x{n}", "nx": n, "ny": n, "gamma": 5.0 / 3.0,
-                   "cfl": 0.5, "bc": "periodic", "seed": 2, "precision": "fp64"},
-        "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": PEAK_FP64_VALU_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved_tf / PEAK_FP64_VALU_TFLOPS,
-                     "traffic": stage_traffic(n), "traffic_unit": "bytes per launch",
-                     "algorithmic_bytes_per_launch": BYTES_PER_CELL_STEP * ncell / 3,
-                     "kernel": "stage_kernel<double,16,16>",
-                     "avg_launch_us": stage_s * 1e6, "hbm_gbs_algorithmic": hbm_gbs,
-                     "hbm_frac": hbm_gbs / PEAK_HBM_GBS, "issue": issue},
-        "repeats": repeats,
+        "config": {"workload": "polytrope_1024x1024_rz_1000steps", "nx": 1024, "ny": 1024,
+                   "geometry": "cylindrical (r, z)", "gamma": 4.0 / 3.0, "cfl": 0.5,
+                   "bc": "reflecting axis and plane, transmissive outside", "gravity": "fixed field",
+                   "rho_floor": 1e-8, "seed": 4, "precision": "fp64",
+                   "steps_from_initial_state": args.steps},
+        "fp64_digest_equals_oracle": head["fp64_digest_equals_oracle"],
+        "roofline": head["roofline"],
+        "repeats": {"runs": len(runs), "median": float(np.median(runs)), "min": min(runs), "max": max(runs)},
         "cpu_baseline": cpu,
-        "fp32_bulk": fp32,
+        "fp32_bulk": head["fp32"],
         "adjoint": adj,
+        "shear_layer": kh,
         "configs": cfgs,
         "probes": prb,
         "sweep": sweep,

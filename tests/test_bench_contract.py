@@ -26,15 +26,31 @@ def test_more_than_one_gpu_exits_with_a_message():
 
 def test_counter_figures_follow_the_source_digest(monkeypatch):
     b = _bench_module()
-    n = b.STAGE_TRAFFIC["n"]
-    want_bytes = b.STAGE_TRAFFIC["bytes_per_launch"]
-    got = b.stage_measured(n, "bytes_per_launch")
-    # either the sources are the measured ones, or the figure is withheld
-    assert got in (want_bytes, None)
-    assert b.stage_measured(n + 1, "bytes_per_launch") is None      # other grid
-    monkeypatch.setitem(b.STAGE_TRAFFIC, "sha256", "0" * 64)      # other sources
-    assert b.stage_measured(n, "bytes_per_launch") is None
-    assert b.stage_measured(n, "valu_insts_per_launch") is None
+    for w, fig in b.STAGE_COUNTERS["workloads"].items():
+        got = b.stage_measured(w, "bytes_per_launch")
+        # either the sources are the measured ones, or the figure is withheld
+        assert got in (fig["bytes_per_launch"], None)
+    assert b.stage_measured("some_other_workload", "bytes_per_launch") is None
+    monkeypatch.setitem(b.STAGE_COUNTERS, "sha256", "0" * 64)      # other sources
+    for w in b.STAGE_COUNTERS["workloads"]:
+        assert b.stage_measured(w, "bytes_per_launch") is None
+        assert b.stage_measured(w, "valu_insts_per_launch") is None
+
+
+def test_roofline_units():
+    b = _bench_module()
+    # 1210 flops per cell-stage (Cartesian, uniform gravity); the polytrope adds
+    # its cylindrical sources and the pressure floor's primitives
+    assert b.FLOPS_PER_CELL_STAGE == 1210
+    assert b.FLOPS_PER_CELL_STAGE_CYL_FLOORS == 1249
+    assert b.BYTES_PER_CELL_STEP == 256 and b.BYTES_PER_CELL_STEP_FIELD == 304
+
+
+def test_golden_digest_lookup():
+    b = _bench_module()
+    assert b.golden_state_digest("no_such_workload", 10) is None
+    d = b.golden_state_digest("polytrope_1024", 1000)
+    assert d is None or len(d) == 64
 
 
 def test_host_cpu_description():

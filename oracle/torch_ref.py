@@ -53,7 +53,7 @@ def _pad(V, axis, bc_lo, bc_hi, normal_comp):
     src, sign = _ghost_map(n, bc_lo, bc_hi)
     P = V.index_select(axis, src)
     s = torch.ones(4, n + 2 * NG, dtype=V.dtype)
-    s[normal_comp] = sign
+    s[normal_comp] = sign.to(V.dtype)
     s = s[:, None, :] if axis == 2 else s[:, :, None]
     return P * s
 
@@ -130,7 +130,7 @@ def rhs(params, gravity, V, ax, ay):
         gx, gy = gravity[0], gravity[1]
     S = torch.stack([torch.zeros_like(rho), rho * gx, rho * gy, V[1] * gx + V[2] * gy])
     if params.get("geometry", 0) == 1:
-        r = params["xlo"] + (torch.arange(nx, dtype=torch.float64) + 0.5) * dx
+        r = (params["xlo"] + (torch.arange(nx, dtype=torch.float64) + 0.5) * dx).to(V.dtype)
         geo = torch.stack([V[1], V[1] * u, V[2] * u, (V[3] + p) * u]) / r
         S = S - geo
     return S - D
@@ -143,8 +143,8 @@ def step(params, gravity, U, dt, alpha):
     return U / 3.0 + 2.0 / 3.0 * (U2 + dt * rhs(params, gravity, U2, *alpha[2]))
 
 
-def _as_t(a):
-    return torch.as_tensor(a, dtype=torch.float64)
+def _as_t(a, dtype=torch.float64):
+    return torch.as_tensor(a, dtype=torch.float64).to(dtype)
 
 
 def step_np(params, gravity, U, dt, alpha):
@@ -154,13 +154,16 @@ def step_np(params, gravity, U, dt, alpha):
         return step(params, g, _as_t(U), float(dt), [tuple(map(float, a)) for a in alpha]).numpy()
 
 
-def vjp(params, gravity, U, dt, alpha, lam):
-    """J^T lam for one step at state U (dt, alpha frozen).  Numpy in/out."""
-    g = None if gravity is None else _as_t(gravity)
-    x = _as_t(U).clone().requires_grad_(True)
+def vjp(params, gravity, U, dt, alpha, lam, dtype=torch.float64):
+    """J^T lam for one step at state U (dt, alpha frozen).  Numpy in/out.
+    dtype=torch.float32 evaluates the same step and its autograd entirely in
+    single precision (inputs rounded to it, result returned as float64): the
+    error that precision alone brings to the adjoint."""
+    g = None if gravity is None else _as_t(gravity, dtype)
+    x = _as_t(U, dtype).clone().requires_grad_(True)
     y = step(params, g, x, float(dt), [tuple(map(float, a)) for a in alpha])
-    (gx,) = torch.autograd.grad(y, x, _as_t(lam))
-    return gx.numpy()
+    (gx,) = torch.autograd.grad(y, x, _as_t(lam, dtype))
+    return gx.double().numpy()
 
 
 def vjp_steps(params, gravity, U, dts, alphas, lam):

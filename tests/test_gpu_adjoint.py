@@ -3,14 +3,24 @@ reference adjoint: autograd through the plain-PyTorch FP64 step of the oracle
 package (itself pinned against central differences of the C oracle).
 
 The adjoint is not bit-exact (its sums run in a different order than
-autograd's); the bound is written per test: FP64 relative error of the whole
-vector (L1) <= 1e-11 -- where the smoothness indicators are ~eps (flat data)
-the weight derivatives carry factors up to 1/(eps + beta) ~ 1e6, which lift
-the usual 1e-16-level rounding of the sums to ~1e-12 on such states.  FP32-bulk <= 1e-3: the split fluxes are held in FP32
-(relative rounding 6e-8), and the adjoint differentiates the WENO weights
-through the smoothness indicators, whose neighbour differences d ~ 1e-4 |v|
-in nearly flat regions keep only ~3-4 significant digits; the forward step is
-insensitive to that error (weights saturate), its derivative is not.
+autograd's).  Every test prints its error; the bounds are about three times
+the largest error measured (the adjoint's arithmetic has a fixed order, so the
+errors are the same on every run):
+
+* FP64 stage adjoint, relative L1 error of the whole vector: largest measured
+  2.8e-14 (the 1024^2 sine-mode shear layer; 2.2e-14 for the 300-cell tube,
+  <= 1.4e-14 on every small grid, boundary set and geometry), bound 8e-14.
+  FP64 rollout gradient (64^2, 24 steps): 4.6e-16 of its largest component,
+  bound 1e-15.
+* FP32-bulk: what single precision alone costs is measured in each test by
+  evaluating the same reference in float32 (inputs rounded, every operation
+  and its autograd in single precision).  The device's FP32-bulk adjoint,
+  which keeps the state and the stage combination in FP64, must be no less
+  accurate than that: stage adjoint 3.7e-4 against 4.6e-4 on the 48^2 shear
+  layer (flat layers: the weight derivatives act on smoothness indicators of
+  nearly equal neighbours, which single precision resolves to a few digits),
+  1.1e-5 against 1.3e-5 on the 64 x 128 walled box; rollout gradient 1.2e-7
+  against 4.2e-7, and within 3.7e-7 (three times the measured).
 """
 import numpy as np
 import pytest
@@ -20,6 +30,9 @@ from paper_1507_08549_amd import inputs
 pytestmark = pytest.mark.gpu
 
 P, T, R = inputs.PERIODIC, inputs.TRANSMISSIVE, inputs.REFLECTING
+FP64_BOUND = 8e-14
+FP64_ROLLOUT_BOUND = 1e-15
+FP32_ROLLOUT_BOUND = 3.7e-7
 
 
 @pytest.fixture(scope="module")
@@ -82,7 +95,8 @@ def test_step_vjp_matches_reference(torch, hydro, oracle_mod, shape, bc, geometr
     s = hydro.Solver(prm)
     got = s.step_vjp(_dev(torch, U0), dt, al, _dev(torch, lam)).cpu().numpy()
     err = _rel_l1(got, want)
-    assert err <= 1e-11, err
+    print(f"ADJ fp64 step {ny}x{nx} bc {bc} geometry {geometry}: {err:.3e}", flush=True)
+    assert err <= FP64_BOUND, err
 
 
 def test_step_vjp_full_size(torch, hydro, oracle_mod):
@@ -98,7 +112,9 @@ def test_step_vjp_full_size(torch, hydro, oracle_mod):
     lam = np.random.default_rng(3).standard_normal(U0.shape)
     want = torch_ref.vjp(prm, None, U0, dt, al, lam)
     got = hydro.Solver(prm).step_vjp(_dev(torch, U0), dt, al, _dev(torch, lam)).cpu().numpy()
-    assert _rel_l1(got, want) <= 1e-11
+    err = _rel_l1(got, want)
+    print(f"ADJ fp64 step 1024x1024 sine-mode shear layer: {err:.3e}", flush=True)
+    assert err <= FP64_BOUND
 
 
 @pytest.mark.parametrize("n", [7, 300], ids=lambda n: f"n{n}")
@@ -113,7 +129,9 @@ def test_step_vjp_1d(torch, hydro, oracle_mod, n):
     lam = np.random.default_rng(5).standard_normal(U0.shape)
     want = torch_ref.vjp(prm, None, U0, dt, al, lam)
     got = hydro.Solver(prm).step_vjp(_dev(torch, U0), dt, al, _dev(torch, lam)).cpu().numpy()
-    assert _rel_l1(got, want) <= 1e-11
+    err = _rel_l1(got, want)
+    print(f"ADJ fp64 step 1D n={n}: {err:.3e}", flush=True)
+    assert err <= FP64_BOUND
 
 
 def test_step_vjp_gravity_field(torch, hydro, oracle_mod):
@@ -131,7 +149,9 @@ def test_step_vjp_gravity_field(torch, hydro, oracle_mod):
     want = torch_ref.vjp(prm, g, U0, dt, al, lam)
     s = hydro.Solver(prm, gravity=_dev(torch, g))
     got = s.step_vjp(_dev(torch, U0), dt, al, _dev(torch, lam)).cpu().numpy()
-    assert _rel_l1(got, want) <= 1e-11
+    err = _rel_l1(got, want)
+    print(f"ADJ fp64 step gravity field: {err:.3e}", flush=True)
+    assert err <= FP64_BOUND
 
 
 @pytest.mark.parametrize("case", ["kh48", "walls64x128"])
@@ -151,9 +171,13 @@ def test_step_vjp_fp32_bulk(torch, hydro, oracle_mod, case):
     _, al = o.step(U0, dt)
     lam = np.random.default_rng(8).standard_normal(U0.shape)
     want = torch_ref.vjp(prm, None, U0, dt, al, lam)
+    # what single precision alone costs: the same reference evaluated in float32
+    e_prec = _rel_l1(torch_ref.vjp(prm, None, U0, dt, al, lam, dtype=torch.float32), want)
     s = hydro.Solver(prm, precision=hydro.FP32_BULK)
     got = s.step_vjp(_dev(torch, U0), dt, al, _dev(torch, lam)).cpu().numpy()
-    assert _rel_l1(got, want) <= 1e-3
+    err = _rel_l1(got, want)
+    print(f"ADJ fp32 step {case}: device {err:.3e}, float32 reference {e_prec:.3e}", flush=True)
+    assert err <= e_prec, (err, e_prec)
 
 
 def test_floors_rejected_by_vjp(torch, hydro):
@@ -201,7 +225,9 @@ def test_rollout_gradient_matches_reference_and_differences(torch, hydro, oracle
     (gr,) = torch.autograd.grad(Jr, ta)
     gr = gr.numpy()
     assert abs(J.item() - Jr.item()) <= 1e-13 * abs(Jr.item())
-    assert np.abs(g - gr).max() <= 1e-10 * np.abs(gr).max(), (g, gr)
+    print(f"ADJ fp64 rollout 64^2 24 steps: max |g - g_ref| / max |g_ref| {np.abs(g - gr).max() / np.abs(gr).max():.3e}",
+          flush=True)
+    assert np.abs(g - gr).max() <= FP64_ROLLOUT_BOUND * np.abs(gr).max(), (g, gr)
 
     # (b) central differences of the device forward with the frozen schedule
     def J_of(avec):
@@ -216,6 +242,40 @@ def test_rollout_gradient_matches_reference_and_differences(torch, hydro, oracle
         e[k] = h
         fd = (J_of(a_np + e) - J_of(a_np - e)) / (2 * h)
         assert abs(fd - g[k]) <= 1e-6 * np.abs(g).max(), (k, fd, g[k])
+
+
+def test_fp32_bulk_rollout_gradient(torch, hydro, oracle_mod):
+    """The sine-mode shear layer on 64^2, 24 steps, checkpoints every 5, in
+    FP32-bulk: the gradient of the final y-kinetic energy with respect to the 8
+    mode amplitudes against the FP64 reference gradient (autograd through the
+    plain-PyTorch step along the oracle's schedule), beside what single
+    precision alone costs (the same reference evaluated in float32)."""
+    from oracle import torch_ref
+    from paper_1507_08549_amd.autograd import rollout
+    n, K, steps = 64, 8, 24
+    prm = inputs.kh_sine_params(n)
+    a_np = inputs.kh_sine_amplitudes(K, seed=5) * 20.0
+    o = oracle_mod.Oracle(prm)
+    _, _, dts, als = o.run(inputs.kh_sine_state(a_np, prm), steps)
+
+    def ref_grad(dtype):
+        ta = torch.tensor(a_np, dtype=torch.float64, requires_grad=True)
+        y = inputs.kh_sine_state(ta, prm).to(dtype)
+        for dt, al in zip(dts, als):
+            y = torch_ref.step(prm, None, y, float(dt), [tuple(map(float, r)) for r in al])
+        (g,) = torch.autograd.grad(_objective(torch, y, prm), ta)
+        return g.double().numpy()
+
+    g64, g32 = ref_grad(torch.float64), ref_grad(torch.float32)
+    s = hydro.Solver(prm, precision=hydro.FP32_BULK)
+    a = torch.tensor(a_np, dtype=torch.float64, device="cuda", requires_grad=True)
+    UN = rollout(inputs.kh_sine_state(a, prm), s, steps, ckpt_every=5)
+    (g,) = torch.autograd.grad(_objective(torch, UN, prm), a)
+    g = g.cpu().numpy()
+    err = np.linalg.norm(g - g64) / np.linalg.norm(g64)
+    e_prec = np.linalg.norm(g32 - g64) / np.linalg.norm(g64)
+    print(f"ADJ fp32 rollout 64^2 24 steps: device {err:.3e}, float32 reference {e_prec:.3e}", flush=True)
+    assert err <= e_prec and err <= FP32_ROLLOUT_BOUND, (err, e_prec)
 
 
 def test_saved_stage_states_reproduce_step_and_vjp(torch, hydro, oracle_mod):
@@ -245,7 +305,7 @@ def test_saved_stage_states_reproduce_step_and_vjp(torch, hydro, oracle_mod):
     b = s.step_vjp_saved(_dev(torch, U0), U1, U2, dt, al, lam)
     assert torch.equal(a, b)
     ref = torch_ref.vjp(prm, None, U0, dt, al, lam.cpu().numpy())
-    assert _rel_l1(b.cpu().numpy(), ref) <= 1e-11
+    assert _rel_l1(b.cpu().numpy(), ref) <= FP64_BOUND
 
 
 def test_run_save_keeps_every_state(torch, hydro, oracle_mod):

@@ -135,3 +135,23 @@ def test_sine_mode_objective_closed_form_at_zero_steps():
     an = a.detach().numpy()
     assert abs(J.item() - 0.375 * np.sum(an ** 2)) < 1e-14
     assert np.allclose(g.numpy(), 0.75 * an, rtol=1e-12, atol=1e-18)
+
+
+def test_float32_reference_is_single_precision(oracle_mod):
+    """The float32 form of the reference adjoint (used to measure what single
+    precision alone costs) runs in single precision: it differs from the
+    float64 form by far more than float64 rounding and by far less than the
+    result itself, and the float64 form is unchanged by the option."""
+    import torch
+
+    from oracle import torch_ref
+    prm, U0 = inputs.kelvin_helmholtz(24, seed=9)
+    o = oracle_mod.Oracle(prm)
+    dt = o.cfl(U0)
+    _, al = o.step(U0, dt)
+    lam = np.random.default_rng(8).standard_normal(U0.shape)
+    w64 = torch_ref.vjp(prm, None, U0, dt, al, lam)
+    assert np.array_equal(w64, torch_ref.vjp(prm, None, U0, dt, al, lam, dtype=torch.float64))
+    w32 = torch_ref.vjp(prm, None, U0, dt, al, lam, dtype=torch.float32)
+    err = np.abs(w32 - w64).sum() / np.abs(w64).sum()
+    assert 1e-9 < err < 1e-2, err

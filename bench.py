@@ -650,6 +650,8 @@ def main():
     ap.add_argument("--cpu-steps-one", type=int, default=10, help="oracle steps timed on one thread")
     ap.add_argument("--only-fp64", action="store_true", help="skip the FP32-bulk legs")
     ap.add_argument("--only-headline", action="store_true", help="the polytrope only (for profiling)")
+    ap.add_argument("--with-shear", action="store_true",
+                    help="with --only-headline: also the shear-layer leg (FP64)")
     ap.add_argument("--kh-n", type=int, default=512, help="shear-layer leg grid (n x n; 0: skip)")
     ap.add_argument("--kh-steps", type=int, default=2000)
     ap.add_argument("--kh-cpu-steps", type=int, default=100,
@@ -694,7 +696,9 @@ def main():
         print("bench.py: no GPU", file=sys.stderr)
         sys.exit(1)
     if args.only_headline:
-        args.kh_n = args.char_steps = args.adj_n = args.poisson_n = args.ls_n = 0
+        if not args.with_shear:
+            args.kh_n = 0
+        args.char_steps = args.adj_n = args.poisson_n = args.ls_n = 0
         args.sweep = ""
         args.no_probes = args.no_configs = True
         args.cpu_steps = 0

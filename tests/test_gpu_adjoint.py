@@ -7,9 +7,14 @@ autograd's).  Every test prints its error; the bounds are about three times
 the largest error measured (the adjoint's arithmetic has a fixed order, so the
 errors are the same on every run):
 
-* FP64 stage adjoint, relative L1 error of the whole vector: largest measured
-  2.8e-14 (the 1024^2 sine-mode shear layer; 2.2e-14 for the 300-cell tube,
-  <= 1.4e-14 on every small grid, boundary set and geometry), bound 8e-14.
+* FP64 stage adjoint, relative L1 error of the whole vector: on random states
+  largest measured 2.8e-14 (the 1024^2 sine-mode shear layer; 2.2e-14 for the
+  300-cell tube, <= 1.4e-14 on every small grid, boundary set and geometry),
+  bound 8e-14.  On shear-layer states with flat layers and cell noise, 1.1e-12
+  to 1.2e-12 on every grid and boundary set, bound 3.5e-12: there the
+  smoothness indicators are ~0, the weight derivatives carry factors up to
+  1/(eps + beta) ~ 1e6, and the rounding differences of two FP64 summation
+  orders grow by that much.
   FP64 rollout gradient (64^2, 24 steps): 4.6e-16 of its largest component,
   bound 1e-15.
 * FP32-bulk: what single precision alone costs is measured in each test by
@@ -31,6 +36,7 @@ pytestmark = pytest.mark.gpu
 
 P, T, R = inputs.PERIODIC, inputs.TRANSMISSIVE, inputs.REFLECTING
 FP64_BOUND = 8e-14
+FP64_FLAT_BOUND = 3.5e-12
 FP64_ROLLOUT_BOUND = 1e-15
 FP32_ROLLOUT_BOUND = 3.7e-7
 
@@ -115,6 +121,27 @@ def test_step_vjp_full_size(torch, hydro, oracle_mod):
     err = _rel_l1(got, want)
     print(f"ADJ fp64 step 1024x1024 sine-mode shear layer: {err:.3e}", flush=True)
     assert err <= FP64_BOUND
+
+
+@pytest.mark.parametrize("bc", BCS, ids=lambda b: "".join("PTR"[k] for k in b))
+@pytest.mark.parametrize("n, seed", [(40, 13), (64, 2), (48, 9)])
+def test_step_vjp_flat_layers(torch, hydro, oracle_mod, bc, n, seed):
+    """Shear-layer states, whose layers are flat: there the smoothness
+    indicators are ~0, the weight derivatives carry factors up to
+    1/(eps + beta) ~ 1e6, and rounding differences between two FP64 orders of
+    summation grow by that much."""
+    from oracle import torch_ref
+    prm, U0 = inputs.kelvin_helmholtz(n, seed=seed)
+    prm["bc"] = list(bc)
+    o = oracle_mod.Oracle(prm)
+    dt = o.cfl(U0)
+    _, al = o.step(U0, dt)
+    lam = np.random.default_rng(4).standard_normal(U0.shape)
+    want = torch_ref.vjp(prm, None, U0, dt, al, lam)
+    got = hydro.Solver(prm).step_vjp(_dev(torch, U0), dt, al, _dev(torch, lam)).cpu().numpy()
+    err = _rel_l1(got, want)
+    print(f"ADJ fp64 flat-layer step {n}^2 seed {seed} bc {bc}: {err:.3e}", flush=True)
+    assert err <= FP64_FLAT_BOUND
 
 
 @pytest.mark.parametrize("n", [7, 300], ids=lambda n: f"n{n}")
@@ -305,7 +332,9 @@ def test_saved_stage_states_reproduce_step_and_vjp(torch, hydro, oracle_mod):
     b = s.step_vjp_saved(_dev(torch, U0), U1, U2, dt, al, lam)
     assert torch.equal(a, b)
     ref = torch_ref.vjp(prm, None, U0, dt, al, lam.cpu().numpy())
-    assert _rel_l1(b.cpu().numpy(), ref) <= FP64_BOUND
+    err = _rel_l1(b.cpu().numpy(), ref)
+    print(f"ADJ fp64 saved-state step, 40^2 shear layer: {err:.3e}", flush=True)
+    assert err <= FP64_FLAT_BOUND
 
 
 def test_run_save_keeps_every_state(torch, hydro, oracle_mod):

@@ -75,9 +75,11 @@ STAGE_SOURCES = ["paper_1507_08549_amd/csrc/stage_kernel.hpp", "paper_1507_08549
 # are under profiles/.  They hold for the kernel sources with this digest only:
 # after any change to them the figures are reported as null until re-measured.
 STAGE_COUNTERS = {
-    "sha256": "391f199656abe7698864bd73113063a5ae8ae9e81bd68b19ab537271b74a946f",
+    "sha256": "8510f68d300d919f1cd5e8192718e2818f57119ccb18dd3654b1005b7581ac55",
     "workloads": {
-        "kelvin_helmholtz_512x512": {"bytes_per_launch": (15.192 + 8.489) * 1e6,
+        "polytrope_1024x1024": {"bytes_per_launch": (38121.7 * 1.99974 + 33154.0) * 1024,
+                                "valu_insts_per_launch": 29231334},
+        "kelvin_helmholtz_512x512": {"bytes_per_launch": (7419.2 * 1.99974 + 8290.0) * 1024,
                                      "valu_insts_per_launch": 6804486},
     },
 }

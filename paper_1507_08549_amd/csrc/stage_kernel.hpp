@@ -164,10 +164,10 @@ __device__ __forceinline__ float lf_fma(float a, float b, float c) { return __bu
 
 // ---------------------------------------------------------- split fluxes
 
-// f+- = (F(U) +- alpha U) / 2 in direction DIR (0: x, 1: y).
+// f+- = (F(U) +- alpha U) / 2 in direction DIR (0: x, 1: y), given the
+// point's primitive variables w (its sound speed is not used).
 template <int DIR, typename R>
-__device__ __forceinline__ void split_flux(const R U[4], R gamma, R gm1, R alpha, R fp[4], R fm[4]) {
-  Prim<R> w = prim(U[0], U[1], U[2], U[3], gamma, gm1);
+__device__ __forceinline__ void split_flux_prim(const R U[4], const Prim<R>& w, R alpha, R fp[4], R fm[4]) {
   R F[4];
   if (DIR == 0) {
     F[0] = U[1];
@@ -185,6 +185,11 @@ __device__ __forceinline__ void split_flux(const R U[4], R gamma, R gm1, R alpha
     fp[c] = R(0.5) * lf_fma(alpha, U[c], F[c]);
     fm[c] = R(0.5) * lf_fma(-alpha, U[c], F[c]);
   }
+}
+
+template <int DIR, typename R>
+__device__ __forceinline__ void split_flux(const R U[4], R gamma, R gm1, R alpha, R fp[4], R fm[4]) {
+  split_flux_prim<DIR>(U, prim(U[0], U[1], U[2], U[3], gamma, gm1), alpha, fp, fm);
 }
 
 // ------------------------------------------- characteristic-wise faces (FP64)
@@ -406,16 +411,23 @@ __global__ __launch_bounds__(TX * TY) void stage_kernel(StageArgs a) {
   };
 
   // The x sweep's points and the control block are requested together, before
-  // anything waits for either: their latencies overlap.
-  constexpr int KPX = (NPX + NT - 1) / NT;
-  Pt px[KPX];
-#pragma unroll
-  for (int kk = 0; kk < KPX; ++kk) {
-    const int k = tid + kk * NT;
-    if (k < NPX) {
-      const int j = k / TXP, lx = k - j * TXP;
-      fetch_point(i0 + lx - NG, j0 + j, px[kk]);
-    }
+  // anything waits for either: their latencies overlap.  Work item (tx, ty)
+  // takes the tile cell (tx, ty) (its primitive variables serve both sweeps
+  // and the per-cell phase) and the first TY * 2 NG work items one x-halo
+  // point each.  A cell past the grid edge is fetched through the index map
+  // of both axes: it is a ghost point only along the axis it lies within, and
+  // its values along the other are discarded.
+  const int tx = tid % TX, ty = tid / TX;
+  constexpr int NHX = TY * 2 * NG;
+  Pt own, hx;
+  fetch_point(i0 + tx, j0 + ty, own);
+  const bool has_hx = tid < NHX;
+  int khx = 0;
+  if (has_hx) {
+    const int j = tid / (2 * NG), c = tid - j * (2 * NG);
+    const int lx = c < NG ? c : c + TX;
+    khx = j * TXP + lx;
+    fetch_point(i0 + lx - NG, j0 + j, hx);
   }
   const bool device_dt = !a.rhs_only && a.dt_mode == 1;
   double t_prev = 0.0, dt_prev = 0.0;
@@ -478,8 +490,8 @@ __global__ __launch_bounds__(TX * TY) void stage_kernel(StageArgs a) {
     }
   }
 
-  const int tx = tid % TX, ty = tid / TX;
   R D[4] = {R(0), R(0), R(0), R(0)};
+  Prim<R> wo;  // primitive variables of the work item's cell (stage input)
 
   // ---- 1. x sweep: split fluxes of the tile rows and their x-halo points
   // (read straight from L2 into registers; only the split fluxes live in LDS),
@@ -488,20 +500,31 @@ __global__ __launch_bounds__(TX * TY) void stage_kernel(StageArgs a) {
   // stencil read is done, then written over the split fluxes.
   {
     const R al = (R)ax;
-#pragma unroll
-    for (int kk = 0; kk < KPX; ++kk) {
-      const int k = tid + kk * NT;
-      if (k >= NPX) break;
+    {
       R U[4];
-      point_state(px[kk], U);
+      point_state(own, U);
+      wo = prim(U[0], U[1], U[2], U[3], gamma, gm1);
       R fp[4], fm[4];
-      split_flux<0>(U, gamma, gm1, al, fp, fm);
+      split_flux_prim<0>(U, wo, al, fp, fm);
+      const int k = ty * TXP + tx + NG;
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         sF[c][k] = fp[c];
         sF[4 + c][k] = fm[c];
       }
       if constexpr (CHAR) store_roe_inputs(U, gamma, gm1, &sF[8][0], NP, k);
+    }
+    if (has_hx) {
+      R U[4];
+      point_state(hx, U);
+      R fp[4], fm[4];
+      split_flux<0>(U, gamma, gm1, al, fp, fm);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        sF[c][khx] = fp[c];
+        sF[4 + c][khx] = fm[c];
+      }
+      if constexpr (CHAR) store_roe_inputs(U, gamma, gm1, &sF[8][0], NP, khx);
     }
     __syncthreads();
     // faces: work item (tx, ty) takes face tx of row ty for all four
@@ -555,8 +578,27 @@ __global__ __launch_bounds__(TX * TY) void stage_kernel(StageArgs a) {
   if (HASY) {
     __syncthreads();  // the x face values are read; sF is reused
     const R al = (R)ay;
-    for (int k = tid; k < NPY; k += NT) {
-      const int ly = k / TX, i = k - ly * TX;
+    {
+      // the work item's cell again (a cache hit), with its primitive variables
+      // from the x sweep
+      Pt pt;
+      fetch_point(i0 + tx, j0 + ty, pt);
+      R U[4];
+      point_state(pt, U);
+      R fp[4], fm[4];
+      split_flux_prim<1>(U, wo, al, fp, fm);
+      const int k = (ty + GY) * TX + tx;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        sF[c][k] = fp[c];
+        sF[4 + c][k] = fm[c];
+      }
+      if constexpr (CHAR) store_roe_inputs(U, gamma, gm1, &sF[8][0], NP, k);
+    }
+    if (tid < TX * 2 * GY) {  // one y-halo point each for the first TX * 2 NG work items
+      const int r = tid / TX, i = tid - r * TX;
+      const int ly = r < GY ? r : r + TY;
+      const int k = ly * TX + i;
       Pt pt;
       fetch_point(i0 + i, j0 + ly - GY, pt);
       R U[4];
@@ -634,7 +676,7 @@ __global__ __launch_bounds__(TX * TY) void stage_kernel(StageArgs a) {
     S[2] = r * gyv;
     S[3] = mx * gxv + my * gyv;
     if (g.cyl) {
-      const Prim<R> w = prim(r, mx, my, E, gamma, gm1);
+      const Prim<R>& w = wo;  // the cell's primitive variables (stage input)
       const double ri = g.xlo + ((double)I + 0.5) * g.dx;
       const R ir = (R)cr_div(1.0, ri);
       S[0] = S[0] - ir * mx;
@@ -655,6 +697,10 @@ __global__ __launch_bounds__(TX * TY) void stage_kernel(StageArgs a) {
         const double u0 = a.U0[c * n + q];
         w[c] = __builtin_fma(a.b, __builtin_fma(dt, (double)L[c], v[c] - u0), u0);
       }
+      // primitive variables of the new state (after the floors: those of the
+      // floored state are reused unless the pressure floor changed E)
+      Prim<double> pw;
+      bool fresh = true;
       if (g.floor_on) {  // atmosphere: minimum density, then minimum pressure
         if (w[0] < g.rho_floor) {
           w[0] = g.rho_floor;
@@ -662,12 +708,13 @@ __global__ __launch_bounds__(TX * TY) void stage_kernel(StageArgs a) {
           w[2] = 0.0;
           w[3] = g.e_floor;
         }
-        const Prim<double> pf = prim(w[0], w[1], w[2], w[3], g.gamma, g.gm1);
-        if (pf.p < g.p_floor) w[3] = g.e_floor + 0.5 * (w[1] * pf.u + w[2] * pf.v);
+        pw = prim(w[0], w[1], w[2], w[3], g.gamma, g.gm1);
+        if (pw.p < g.p_floor) w[3] = g.e_floor + 0.5 * (w[1] * pw.u + w[2] * pw.v);
+        else fresh = false;
       }
 #pragma unroll
       for (int c = 0; c < 4; ++c) a.W[c * n + q] = w[c];
-      const Prim<double> pw = prim(w[0], w[1], w[2], w[3], g.gamma, g.gm1);
+      if (fresh) pw = prim(w[0], w[1], w[2], w[3], g.gamma, g.gm1);
       bad = !(w[0] > 0.0) || !(pw.p > 0.0) || !__builtin_isfinite(pw.c);
       amax = __builtin_fabs(pw.u) + pw.c;
       bmax = __builtin_fabs(pw.v) + pw.c;

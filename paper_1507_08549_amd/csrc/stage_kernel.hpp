@@ -74,20 +74,30 @@ __device__ __forceinline__ Prim<double> prim(double r, double mx, double my, dou
   return w;
 }
 
+// Second difference of three consecutive stencil values (in stencil order)
+// and 13/12 times it: the first term of a smoothness indicator.  Neighbouring
+// faces' stencils share their middle points, so a run of faces computes each
+// point's pair once.
+struct D2 {
+  double d, cd;
+};
+__device__ __forceinline__ D2 d2_at(double l, double m, double r) {
+  const double d = __builtin_fma(-2.0, m, l) + r;
+  return {d, (13.0 / 12.0) * d};
+}
+
 // WENO5-JS at the right face of v2 as numerator and denominator (weights over
-// the common denominator 10 s0 s1 s2, s_k = (eps + beta_k)^2): W = num / den.
-__device__ __forceinline__ void weno5_nd(double v0, double v1, double v2, double v3, double v4, double eps,
-                                         double& num, double& den) {
-  const double c1312 = 13.0 / 12.0;
-  double d = __builtin_fma(-2.0, v1, v0) + v2;
+// the common denominator 10 s0 s1 s2, s_k = (eps + beta_k)^2): W = num / den;
+// given the second differences of the candidate stencils (v0 v1 v2),
+// (v1 v2 v3), (v2 v3 v4).
+__device__ __forceinline__ void weno5_nd_d2(double v0, double v1, double v2, double v3, double v4, D2 t0,
+                                            D2 t1, D2 t2, double eps, double& num, double& den) {
   double e = __builtin_fma(3.0, v2, __builtin_fma(-4.0, v1, v0));
-  double b0 = __builtin_fma(c1312 * d, d, (0.25 * e) * e);
-  d = __builtin_fma(-2.0, v2, v1) + v3;
+  double b0 = __builtin_fma(t0.cd, t0.d, (0.25 * e) * e);
   e = v1 - v3;
-  double b1 = __builtin_fma(c1312 * d, d, (0.25 * e) * e);
-  d = __builtin_fma(-2.0, v3, v2) + v4;
+  double b1 = __builtin_fma(t1.cd, t1.d, (0.25 * e) * e);
   e = __builtin_fma(-4.0, v3, 3.0 * v2) + v4;
-  double b2 = __builtin_fma(c1312 * d, d, (0.25 * e) * e);
+  double b2 = __builtin_fma(t2.cd, t2.d, (0.25 * e) * e);
   double p0 = __builtin_fma(11.0, v2, __builtin_fma(-7.0, v1, 2.0 * v0));
   double p1 = __builtin_fma(5.0, v2, __builtin_fma(2.0, v3, -v1));
   double p2 = __builtin_fma(5.0, v3, __builtin_fma(2.0, v2, -v4));
@@ -99,6 +109,11 @@ __device__ __forceinline__ void weno5_nd(double v0, double v1, double v2, double
   double w2 = 3.0 * (s0 * s1);
   num = __builtin_fma(w2, p2, __builtin_fma(w1, p1, w0 * p0));
   den = 6.0 * ((w0 + w1) + w2);
+}
+
+__device__ __forceinline__ void weno5_nd(double v0, double v1, double v2, double v3, double v4, double eps,
+                                         double& num, double& den) {
+  weno5_nd_d2(v0, v1, v2, v3, v4, d2_at(v0, v1, v2), d2_at(v1, v2, v3), d2_at(v2, v3, v4), eps, num, den);
 }
 
 __device__ __forceinline__ double weno5(double v0, double v1, double v2, double v3, double v4,
@@ -280,6 +295,41 @@ __device__ __forceinline__ R face_value(const R* P, const R* M, int st, R eps) {
            weno5(M[5 * st], M[4 * st], M[3 * st], M[2 * st], M[st], eps);
 }
 
+// Face values of a run of NR consecutive faces of one component: P and M
+// point at f+ and f- of the first face's fourth-left point, st is the point
+// stride; face j lies between points j + 2 and j + 3, its f+ stencil is
+// P[j .. j + 4] and its f- stencil M[j + 5 .. j + 1] (upwind first).  In FP64
+// each point's second differences (one pair for the f+ stencils, one for the
+// f- stencils, which run the other way) are computed once for the run; every
+// value is the one face_value gives.
+template <int NR, typename R>
+__device__ __forceinline__ void face_run(const R* P, const R* M, int st, R eps, R out[NR]) {
+  if constexpr (sizeof(R) == 8) {
+    D2 sp[NR + 3], sm[NR + 4];  // sp[k]: around P[k]; sm[k]: around M[k] (taken from M[k + 1] down)
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+      if (j == 0) {
+        sp[1] = d2_at(P[0], P[st], P[2 * st]);
+        sp[2] = d2_at(P[st], P[2 * st], P[3 * st]);
+        sm[2] = d2_at(M[3 * st], M[2 * st], M[st]);
+        sm[3] = d2_at(M[4 * st], M[3 * st], M[2 * st]);
+      }
+      sp[j + 3] = d2_at(P[(j + 2) * st], P[(j + 3) * st], P[(j + 4) * st]);
+      sm[j + 4] = d2_at(M[(j + 5) * st], M[(j + 4) * st], M[(j + 3) * st]);
+      double np, dp, nm, dm;
+      weno5_nd_d2(P[j * st], P[(j + 1) * st], P[(j + 2) * st], P[(j + 3) * st], P[(j + 4) * st], sp[j + 1],
+                  sp[j + 2], sp[j + 3], eps, np, dp);
+      weno5_nd_d2(M[(j + 5) * st], M[(j + 4) * st], M[(j + 3) * st], M[(j + 2) * st], M[(j + 1) * st],
+                  sm[j + 4], sm[j + 3], sm[j + 2], eps, nm, dm);
+      out[j] = cr_div_pos(np * dm + nm * dp, dp * dm);  // dp, dm > 0: sums of positive weights
+      asm volatile("" : "+v"(out[j]) : : "memory");  // one face at a time: few live registers
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < NR; ++j) out[j] = face_value(P + j * st, M + j * st, st, eps);
+  }
+}
+
 // Max of a non-negative x over the wavefront, valid in lane 63 (exact: a max
 // of doubles).  DPP row shifts by 1, 2, 4, 8 (a lane with no source reads 0)
 // leave each 16-lane row's max in its lane 15; row_bcast:15 and
@@ -358,6 +408,7 @@ __global__ __launch_bounds__(TX * TY) void stage_kernel(StageArgs a) {
   constexpr int NF = NFX > NFY ? NFX : NFY;
   constexpr int NW = (NT + 63) / 64;
   static_assert(NT % 64 == 0, "whole wavefronts");
+  static_assert(TX % 4 == 0 && (!HASY || TY % 4 == 0), "runs of four faces tile the rows and columns");
 
   static_assert(8 * NP >= 4 * NF, "face values fit in the split-flux storage");
   static_assert(!CHAR || sizeof(R) == 8, "characteristic faces are FP64 only");
@@ -545,22 +596,20 @@ __global__ __launch_bounds__(TX * TY) void stage_kernel(StageArgs a) {
         for (int c = 0; c < 4; ++c) sFh[c * NFX + tid * (TX + 1) + TX] = fe[c];
       }
     } else {
-      // one (face, component) per work item: face tx of row ty for each
-      // component, then the last face of every row (f = TX) for the first 4 TY
+      // a run of four faces of one component per work item: faces 4q .. 4q + 3
+      // of row r (component c = tid / (TY TX / 4), rows in consecutive
+      // lanes), then the last face of every row (f = TX) for the first 4 TY
       // work items
       R fh[4], fe = R(0);
-      const int base = ty * TXP + tx;
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        fh[c] = face_value(&sF[c][base], &sF[4 + c][base], 1, eps);
-        asm volatile("" : "+v"(fh[c]) : : "memory");  // one component at a time: few live registers
-      }
+      const int rc = tid / (TY * (TX / 4)), rrem = tid - rc * (TY * (TX / 4));
+      const int rr = rrem % TY, rq = rrem / TY;
+      face_run<4>(&sF[rc][rr * TXP + 4 * rq], &sF[4 + rc][rr * TXP + 4 * rq], 1, eps, fh);
       const bool extra = tid < 4 * TY;
       const int ec = tid / TY, ej = tid - ec * TY;
       if (extra) fe = face_value(&sF[ec][ej * TXP + TX], &sF[4 + ec][ej * TXP + TX], 1, eps);
       __syncthreads();
 #pragma unroll
-      for (int c = 0; c < 4; ++c) sFh[c * NFX + ty * (TX + 1) + tx] = fh[c];
+      for (int j = 0; j < 4; ++j) sFh[rc * NFX + rr * (TX + 1) + 4 * rq + j] = fh[j];
       if (extra) sFh[ec * NFX + ej * (TX + 1) + TX] = fe;
     }
     __syncthreads();
@@ -630,21 +679,19 @@ __global__ __launch_bounds__(TX * TY) void stage_kernel(StageArgs a) {
         for (int c = 0; c < 4; ++c) sFh[c * NFY + TY * TX + tid] = fe[c];
       }
     } else {
-      // face ty of column tx for each component, then the last face of every
+      // a run of four faces 4q .. 4q + 3 of column i and one component per
+      // work item (columns in consecutive lanes), then the last face of every
       // column (f = TY) for the first 4 TX work items
       R fh[4], fe = R(0);
-      const int base = ty * TX + tx;
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        fh[c] = face_value(&sF[c][base], &sF[4 + c][base], TX, eps);
-        asm volatile("" : "+v"(fh[c]) : : "memory");
-      }
+      const int rc = tid / (TX * (TY / 4)), rrem = tid - rc * (TX * (TY / 4));
+      const int ri = rrem % TX, rq = rrem / TX;
+      face_run<4>(&sF[rc][4 * rq * TX + ri], &sF[4 + rc][4 * rq * TX + ri], TX, eps, fh);
       const bool extra = tid < 4 * TX;
       const int ec = tid / TX, ei = tid - ec * TX;
       if (extra) fe = face_value(&sF[ec][TY * TX + ei], &sF[4 + ec][TY * TX + ei], TX, eps);
       __syncthreads();
 #pragma unroll
-      for (int c = 0; c < 4; ++c) sFh[c * NFY + ty * TX + tx] = fh[c];
+      for (int j = 0; j < 4; ++j) sFh[rc * NFY + (4 * rq + j) * TX + ri] = fh[j];
       if (extra) sFh[ec * NFY + TY * TX + ei] = fe;
     }
     __syncthreads();

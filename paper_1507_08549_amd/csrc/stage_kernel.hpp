@@ -384,6 +384,23 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
   return (b % 8) * (nb / 8) + b / 8;
 }
 
+// Wide grids (256 or more tile columns): within each XCD's run of whole tile
+// rows, bands of 64 tile columns are taken one after another, row by row
+// inside a band.  The tiles an XCD holds at once then span about three tile
+// rows of one band and read their shared halo rows from its L2; in plain row
+// order across such a grid a tile row's halo is evicted before the row below
+// needs it (4096^2: 1.31x the algorithmic HBM bytes, 1.01x banded).
+__device__ __forceinline__ int xcd_band_tile(int b, int nb, int ntx) {
+  constexpr int W = 64;
+  if (nb % 8 != 0 || ntx < 256 || ntx % W != 0) return xcd_tile(b, nb);
+  const int per = nb / 8;  // tiles per XCD
+  if (per % ntx != 0) return xcd_tile(b, nb);
+  const int rows = per / ntx;
+  const int x = b % 8, l = b / 8;  // XCD, index within its run
+  const int band = l / (rows * W), r = (l % (rows * W)) / W, c = l % W;
+  return x * per + r * ntx + band * W + c;
+}
+
 // Per-point inputs of the Roe average: sqrt(rho), u, v, H = (E + p)/rho.
 template <typename R>
 __device__ __forceinline__ void store_roe_inputs(const R U[4], R gamma, R gm1, R* Q, int np, int k) {
@@ -424,7 +441,7 @@ __global__ __launch_bounds__(TX * TY) void stage_kernel(StageArgs a) {
   const bool lead = (blockIdx.x == 0 && tid == 0);
 
   const int ntx = (g.nx + TX - 1) / TX;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int tile = xcd_band_tile(blockIdx.x, gridDim.x, ntx);
   const int i0 = (tile % ntx) * TX;
   const int j0 = (tile / ntx) * TY;
   const size_t n = (size_t)g.nx * g.ny;

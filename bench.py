@@ -75,12 +75,12 @@ STAGE_SOURCES = ["paper_1507_08549_amd/csrc/stage_kernel.hpp", "paper_1507_08549
 # are under profiles/.  They hold for the kernel sources with this digest only:
 # after any change to them the figures are reported as null until re-measured.
 STAGE_COUNTERS = {
-    "sha256": "8510f68d300d919f1cd5e8192718e2818f57119ccb18dd3654b1005b7581ac55",
+    "sha256": "c3249b8e286c6508bbec3d2d1a4b2ecf480124bb016f42c4c1276a8239600408",
     "workloads": {
-        "polytrope_1024x1024": {"bytes_per_launch": (38121.7 * 1.99974 + 33154.0) * 1024,
-                                "valu_insts_per_launch": 29231334},
-        "kelvin_helmholtz_512x512": {"bytes_per_launch": (7419.2 * 1.99974 + 8290.0) * 1024,
-                                     "valu_insts_per_launch": 6804486},
+        "polytrope_1024x1024": {"bytes_per_launch": (36442.5 * 1.99974 + 33154.0) * 1024,
+                                "valu_insts_per_launch": 25828327},
+        "kelvin_helmholtz_512x512": {"bytes_per_launch": (7423.6 * 1.99974 + 8290.0) * 1024,
+                                     "valu_insts_per_launch": 6201945},
     },
 }
 # The potential solver's launch (4 iterations): measured HBM bytes and VALU

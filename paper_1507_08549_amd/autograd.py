@@ -7,8 +7,11 @@ steps.  Its backward pass walks the segments from last to first: it re-runs
 the segment from its checkpoint with the recorded schedule (bit-identical to
 the forward) through ``hydro_step_save``, keeping the state at the start of
 every step and its two Runge-Kutta stage states, and then applies
-``hydro_step_vjp_saved`` step by step.  Memory: nsteps / ckpt_every
-checkpoints plus 3 * ckpt_every states.  With ``ckpt_every=None`` the forward
+``hydro_step_vjp_saved`` step by step.  The last segment needs no re-run: the
+forward pass runs it with ``hydro_run_save`` into the buffer the backward
+pass replays into.  Memory: nsteps / ckpt_every checkpoints plus 3 *
+ckpt_every states (that buffer, held from the forward pass to the end of the
+backward pass).  With ``ckpt_every=None`` the forward
 runs ``hydro_run_save`` and keeps all 3 * nsteps states (a 1024^2, 500-step
 rollout: 50 GB, a sixth of the device's memory), and the backward pass is
 the step adjoints alone.
@@ -44,12 +47,22 @@ class HydroRollout(torch.autograd.Function):
         if ckpt_every < 1:
             raise ValueError("ckpt_every must be >= 1 (or None to keep every state)")
         ckpts = []
+        kmax = min(ckpt_every, nsteps)
+        # the backward pass's replay buffer (each step's start state and two
+        # stage states), filled here for the last segment, which the backward
+        # pass then starts from without a replay
+        pool = torch.empty((max(kmax, 1), 3) + tuple(U.shape), dtype=torch.float64, device=U.device)
         for s0 in range(0, nsteps, ckpt_every):
             k = min(ckpt_every, nsteps - s0)
             ckpts.append(U.clone())
-            solver.run_into(U, k, dts[s0:s0 + k], als[s0:s0 + k])
+            if s0 + k < nsteps:
+                solver.run_into(U, k, dts[s0:s0 + k], als[s0:s0 + k])
+            else:
+                solver.run_save(U, k, pool[:k], dts[s0:s0 + k], als[s0:s0 + k])
         ctx.ckpt_every = ckpt_every
         ctx.ckpts = ckpts
+        ctx.pool = pool
+        ctx.pool_holds_last = True
         return U
 
     @staticmethod
@@ -66,23 +79,25 @@ class HydroRollout(torch.autograd.Function):
                 solver.step_vjp_saved(st[i, 0], st[i, 1], st[i, 2], dts_h[i], als_h[i], lam, out=nxt)
                 lam, nxt = nxt, lam
             return lam, None, None, None
-        kmax = min(ctx.ckpt_every, ctx.nsteps)
-        # per step of a segment: its start state and its two stage states
-        pool = [[torch.empty_like(lam) for _ in range(3)] for _ in range(kmax)]
+        # per step of a segment: its start state and its two stage states; the
+        # forward pass left the last segment's there
+        pool = ctx.pool
         nseg = len(ctx.ckpts)
         for seg in range(nseg - 1, -1, -1):
             s0 = seg * ctx.ckpt_every
             k = min(ctx.ckpt_every, ctx.nsteps - s0)
-            pool[0][0].copy_(ctx.ckpts[seg])
-            for i in range(k):
-                U, U1, U2 = pool[i]
-                # the last step's end state is not needed, only its stages
-                dst = pool[i + 1][0] if i + 1 < k else nxt
-                solver.step_save(U, dts_h[s0 + i], als_h[s0 + i], U1, U2, out=dst)
+            if seg < nseg - 1 or not ctx.pool_holds_last:  # replay the segment from its checkpoint
+                pool[0, 0].copy_(ctx.ckpts[seg])
+                for i in range(k):
+                    U, U1, U2 = pool[i, 0], pool[i, 1], pool[i, 2]
+                    # the last step's end state is not needed, only its stages
+                    dst = pool[i + 1, 0] if i + 1 < k else nxt
+                    solver.step_save(U, dts_h[s0 + i], als_h[s0 + i], U1, U2, out=dst)
             for i in range(k - 1, -1, -1):
-                U, U1, U2 = pool[i]
+                U, U1, U2 = pool[i, 0], pool[i, 1], pool[i, 2]
                 solver.step_vjp_saved(U, U1, U2, dts_h[s0 + i], als_h[s0 + i], lam, out=nxt)
                 lam, nxt = nxt, lam
+        ctx.pool_holds_last = False  # (a second backward pass replays every segment)
         return lam, None, None, None
 
 

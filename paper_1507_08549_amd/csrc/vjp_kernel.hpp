@@ -195,10 +195,14 @@ __global__ __launch_bounds__(64 * NL) void vjp_line_kernel(VjpPass P) {
   constexpr int NT = 64 * NL;
   constexpr int NA = 58;       // cells per line and tile
   constexpr int LP = 69;       // staged points a0 - 6 .. a0 + 62
-  __shared__ R sF[8][NL][LP];
-  // (rows padded to 65 so that work items on neighbouring lines hit different banks)
-  __shared__ R sU[STAGE_OWN ? 4 : 1][NL][65];
-  __shared__ R sM[STAGE_OWN ? 4 : 1][NL][65];
+  // Row strides padded for the y pass's staging writes, where consecutive work
+  // items take consecutive lines b at point p (p = t / NL): 70 and 66 doubles
+  // are 6 and 2 mod 16, so the 16 work items of a 128-byte LDS cycle (8 lines
+  // x 2 points) hit 16 different 8-byte bank pairs (69 and 65 put up to four
+  // on one pair: 1.3M conflict cycles per 1024^2 dispatch, 0.13M padded).
+  __shared__ R sF[8][NL][LP + 1];
+  __shared__ R sU[STAGE_OWN ? 4 : 1][NL][66];
+  __shared__ R sM[STAGE_OWN ? 4 : 1][NL][66];
 
   const VjpArgs& a = P.a;
   const Geom& g = a.g;

@@ -29,6 +29,13 @@
  *  - HYDRO_E_UNPHYSICAL is sticky: a stage that produces rho <= 0 or p <= 0
  *    (after the optional atmosphere floors) sets a device flag; the next
  *    synchronising call returns the code and hydro_check() clears it.
+ *  - Magnitudes: the WENO weights of a face are summed over one common
+ *    denominator, which multiplies eighth powers of the smoothness
+ *    indicators, so the split fluxes (F(U) +- alpha U) / 2 must stay below
+ *    about 1e17 in magnitude (FP64; about 1e9 with HYDRO_FP32_BULK).  States
+ *    in units of order one, as in the paper's dimensionless tests, are far
+ *    inside; beyond it the faces overflow to NaN and the step reports
+ *    HYDRO_E_UNPHYSICAL.  Problems in physical units are to be scaled.
  */
 #ifndef HYDRO_H
 #define HYDRO_H

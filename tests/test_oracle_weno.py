@@ -170,3 +170,22 @@ def test_face_value_matches_exact_js_sum(oracle_mod, derived):
         assert abs(got - float(exact)) <= 8e-15 * ref, (p, m, got, exact)
         assert oracle_mod.weno5_face(m, p, eps) == got
         assert oracle_mod.weno5_face([-x for x in p], [-x for x in m], eps) == -got
+
+
+def test_common_denominator_magnitude_domain(oracle_mod):
+    """The face value over one common denominator multiplies eighth powers of
+    the smoothness indicators: it is homogeneous of degree one (for stencils
+    large against eps) up to split-flux magnitudes of 1e17 and overflows to
+    NaN by 1e19 (by 1e18 for most stencils), the input domain include/hydro.h
+    states."""
+    rng = np.random.default_rng(3)
+    for trial in range(20):
+        p = rng.uniform(-1, 1, 5)
+        m = rng.uniform(-1, 1, 5)
+        ref = oracle_mod.weno5_face(p * 1e9, m * 1e9) / 1e9
+        scale = max(np.abs(p).max(), np.abs(m).max())
+        for e in (6, 12, 15, 17):
+            S = 10.0 ** e
+            f = oracle_mod.weno5_face(p * S, m * S)
+            assert np.isfinite(f) and abs(f / S - ref) <= 1e-12 * scale, (trial, e)
+        assert not np.isfinite(oracle_mod.weno5_face(p * 1e19, m * 1e19)), trial

@@ -126,11 +126,10 @@ def test_mirror_with_gravity_bitwise(oracle_mod):
     assert np.array_equal(_mirror_x(a), b)
 
 
-@pytest.mark.parametrize("geometry", [0, 1])
-@pytest.mark.parametrize("bc", [[P, P, P, P], [T, T, T, T], [R, R, R, R], [R, T, R, T]])
+@pytest.mark.parametrize("bc, geometry", [(bc, geo) for geo in (0, 1)
+                                           for bc in ([P, P, P, P], [T, T, T, T], [R, R, R, R], [R, T, R, T])
+                                           if not (geo == 1 and bc[0] == P)])  # the axis is never periodic
 def test_rest_state_preserved_bitwise(oracle_mod, geometry, bc):
-    if geometry == 1 and bc[0] == P:
-        pytest.skip("the axis of a cylindrical grid is not periodic")
     prm = inputs.make_params(12, 10, 0.0, 1.2, 0.0, 1.0, bc, 1.4, geometry=geometry)
     U = inputs.state_from_primitive(np.full((10, 12), 0.7), 0.0, 0.0, 1.3, 1.4)
     o = oracle_mod.Oracle(prm)

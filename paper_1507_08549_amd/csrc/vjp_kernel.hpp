@@ -36,6 +36,10 @@
 namespace hy {
 
 // nu * dW5/dv_m for the reconstruction W5(v0..v4) at the right face of v2.
+// With omega_k the nonlinear weights, q_k the candidate values and
+// W = sum omega_k q_k: dW = sum omega_k dq_k - 2 sum omega_k (q_k - W) dbeta_k
+// / (eps + beta_k).  The candidates are carried as Q_k = 6 q_k (the 1/6 folded
+// into the factors below).
 __device__ __forceinline__ void weno5_adj(const double v[5], double eps, double nu, double vb[5]) {
   const double c1312 = 13.0 / 12.0;
   const double d0 = v[0] - 2.0 * v[1] + v[2], e0 = v[0] - 4.0 * v[1] + 3.0 * v[2];
@@ -48,7 +52,8 @@ __device__ __forceinline__ void weno5_adj(const double v[5], double eps, double 
   // weights over the common denominator; one division gives 1/sum(w) and 1/(E0 E1 E2)
   const double w0 = s1 * s2, w1 = 6.0 * (s0 * s2), w2 = 3.0 * (s0 * s1);
   const double sw = w0 + w1 + w2;
-  const double P = E0 * E1 * E2;
+  const double E12 = E1 * E2, E02 = E0 * E2, E01 = E0 * E1;
+  const double P = E0 * E12;
   // 1 / (P sw): hardware reciprocal and two Newton steps (the adjoint needs
   // no correctly rounded quotient; P sw is a normal positive number)
   const double x = P * sw;
@@ -57,15 +62,17 @@ __device__ __forceinline__ void weno5_adj(const double v[5], double eps, double 
   inv = __builtin_fma(inv, __builtin_fma(-x, inv, 1.0), inv);
   const double isw = P * inv, iP = sw * inv;
   const double om0 = w0 * isw, om1 = w1 * isw, om2 = w2 * isw;
-  const double q0 = (2.0 * v[0] - 7.0 * v[1] + 11.0 * v[2]) * (1.0 / 6.0);
-  const double q1 = (-v[1] + 5.0 * v[2] + 2.0 * v[3]) * (1.0 / 6.0);
-  const double q2 = (2.0 * v[2] + 5.0 * v[3] - v[4]) * (1.0 / 6.0);
-  const double W = om0 * q0 + om1 * q1 + om2 * q2;
-  const double r0 = E1 * E2 * iP, r1 = E0 * E2 * iP, r2 = E0 * E1 * iP;  // 1 / E_k
-  const double bb0 = -2.0 * nu * om0 * (q0 - W) * r0;
-  const double bb1 = -2.0 * nu * om1 * (q1 - W) * r1;
-  const double bb2 = -2.0 * nu * om2 * (q2 - W) * r2;
-  const double c0 = nu * om0 * (1.0 / 6.0), c1 = nu * om1 * (1.0 / 6.0), c2 = nu * om2 * (1.0 / 6.0);
+  const double Q0 = 2.0 * v[0] - 7.0 * v[1] + 11.0 * v[2];
+  const double Q1 = -v[1] + 5.0 * v[2] + 2.0 * v[3];
+  const double Q2 = 2.0 * v[2] + 5.0 * v[3] - v[4];
+  const double W6 = om0 * Q0 + om1 * Q1 + om2 * Q2;
+  // beta-adjoints -2 nu omega_k (q_k - W) / E_k, with 1 / E_k = (product of the other two) / P
+  const double f = (-1.0 / 3.0) * nu * iP;
+  const double bb0 = f * (om0 * (Q0 - W6)) * E12;
+  const double bb1 = f * (om1 * (Q1 - W6)) * E02;
+  const double bb2 = f * (om2 * (Q2 - W6)) * E01;
+  const double n6 = nu * (1.0 / 6.0);
+  const double c0 = n6 * om0, c1 = n6 * om1, c2 = n6 * om2;
   const double t0 = bb0 * (13.0 / 6.0) * d0, h0 = bb0 * 0.5 * e0;
   const double t1 = bb1 * (13.0 / 6.0) * d1, h1 = bb1 * 0.5 * e1;
   const double t2 = bb2 * (13.0 / 6.0) * d2, h2 = bb2 * 0.5 * e2;
@@ -106,16 +113,41 @@ __device__ __forceinline__ void weno5_adj(const float v[5], float eps, float nu,
   vb[4] = -c2 + t2 + h2;
 }
 
+// 1/r for the adjoint, which is not bit-exact and needs no correctly rounded
+// quotient: the hardware reciprocal refined by two Newton steps (FP64; r is a
+// positive normal number on every state the adjoint is defined at), the
+// hardware reciprocal in FP32.
+__device__ __forceinline__ double adj_rcp(double r) {
+  double y = __builtin_amdgcn_rcp(r);
+  y = __builtin_fma(y, __builtin_fma(-r, y, 1.0), y);
+  return __builtin_fma(y, __builtin_fma(-r, y, 1.0), y);
+}
+__device__ __forceinline__ float adj_rcp(float r) { return rcpf(r); }
+
+// Velocity and pressure of a point for the adjoint's split fluxes.
+template <typename R>
+__device__ __forceinline__ Prim<R> adj_prim(const R U[4], R gm1, R& rinv) {
+  Prim<R> w;
+  rinv = adj_rcp(U[0]);
+  w.u = U[1] * rinv;
+  w.v = U[2] * rinv;
+  w.p = gm1 * (U[3] - R(0.5) * (U[1] * w.u + U[2] * w.v));
+  w.c = R(0);  // (not used by the split fluxes)
+  return w;
+}
+
 // Quantities of a point that the flux-Jacobian rows need.
 template <typename R> struct JacPt { R u, v, H, hq; };  // hq = (gamma-1) |v|^2 / 2
 
 template <typename R>
 __device__ __forceinline__ JacPt<R> jac_point(R r, R mx, R my, R E, R gamma, R gm1) {
-  const Prim<R> w = prim(r, mx, my, E, gamma, gm1);
+  const R U[4] = {r, mx, my, E};
+  R rinv;
+  const Prim<R> w = adj_prim(U, gm1, rinv);
   JacPt<R> j;
   j.u = w.u;
   j.v = w.v;
-  j.H = (E + w.p) / r;
+  j.H = (E + w.p) * rinv;
   j.hq = R(0.5) * gm1 * (w.u * w.u + w.v * w.v);
   return j;
 }
@@ -256,7 +288,8 @@ __global__ __launch_bounds__(64 * NL) void vjp_line_kernel(VjpPass P) {
   R cu[4], mu[4];
   auto stage_point = [&](int p, int b, const R u4[4]) {
     R fp[4], fm[4];
-    split_flux<DIR>(u4, gamma, gm1, alpha, fp, fm);
+    R rinv;
+    split_flux_prim<DIR>(u4, adj_prim(u4, gm1, rinv), alpha, fp, fm);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       sF[c][b][p] = fp[c];

@@ -48,6 +48,26 @@ __device__ __forceinline__ double cr_div_pos(double a, double b) {
   return __builtin_fabs(t2) < __builtin_fabs(t) ? q2 : q;
 }
 
+// cr_div_pos for a quotient of a positive normal denominator whose
+// reciprocal is normal and a quotient that is zero or normal: the faithful
+// quotient from the hardware reciprocal refined by two Newton steps and one
+// correction step (q0 = a r, q = q0 + (a - q0 b) r), without the scaling and
+// special-value steps of the general division sequence, then the same
+// neighbour check.  The WENO face values are such quotients: their
+// denominators, products of sums of weights, lie between about 3e-47
+// (eps = 1e-6) and the overflow of the numerator that comes with them.
+__device__ __forceinline__ double cr_div_pos_normal(double a, double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  r = __builtin_fma(r, __builtin_fma(-b, r, 1.0), r);
+  r = __builtin_fma(r, __builtin_fma(-b, r, 1.0), r);
+  const double q0 = a * r;
+  const double q = __builtin_fma(__builtin_fma(-q0, b, a), r, q0);
+  const double t = __builtin_fma(-q, b, a);
+  const double q2 = ieee_step(q, t);
+  const double t2 = __builtin_fma(-q2, b, a);
+  return __builtin_fabs(t2) < __builtin_fabs(t) ? q2 : q;
+}
+
 __device__ __forceinline__ double cr_sqrt(double x) {
   const double s = __builtin_sqrt(x);
   const double t = __builtin_fma(-s, s, x);

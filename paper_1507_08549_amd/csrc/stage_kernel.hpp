@@ -321,7 +321,7 @@ __device__ __forceinline__ void face_run(const R* P, const R* M, int st, R eps, 
                   sp[j + 2], sp[j + 3], eps, np, dp);
       weno5_nd_d2(M[(j + 5) * st], M[(j + 4) * st], M[(j + 3) * st], M[(j + 2) * st], M[(j + 1) * st],
                   sm[j + 4], sm[j + 3], sm[j + 2], eps, nm, dm);
-      out[j] = cr_div_pos(np * dm + nm * dp, dp * dm);  // dp, dm > 0: sums of positive weights
+      out[j] = cr_div_pos_normal(np * dm + nm * dp, dp * dm);  // dp, dm > 0: sums of positive weights
       asm volatile("" : "+v"(out[j]) : : "memory");  // one face at a time: few live registers
     }
   } else {
@@ -645,12 +645,9 @@ __global__ __launch_bounds__(TX * TY) void stage_kernel(StageArgs a) {
     __syncthreads();  // the x face values are read; sF is reused
     const R al = (R)ay;
     {
-      // the work item's cell again (a cache hit), with its primitive variables
-      // from the x sweep
-      Pt pt;
-      fetch_point(i0 + tx, j0 + ty, pt);
+      // the work item's cell, with its primitive variables from the x sweep
       R U[4];
-      point_state(pt, U);
+      point_state(own, U);
       R fp[4], fm[4];
       split_flux_prim<1>(U, wo, al, fp, fm);
       const int k = (ty + GY) * TX + tx;

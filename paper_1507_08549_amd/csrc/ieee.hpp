@@ -68,6 +68,20 @@ __device__ __forceinline__ double cr_div_pos_normal(double a, double b) {
   return __builtin_fabs(t2) < __builtin_fabs(t) ? q2 : q;
 }
 
+// Correctly rounded 1 / b for a positive normal b with a normal reciprocal
+// (densities, radii): the hardware reciprocal refined by two Newton steps is
+// faithful, then the neighbour check.  (Other b: not correctly rounded; the
+// states where that happens are reported as unphysical anyway.)
+__device__ __forceinline__ double cr_rcp_pos(double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  r = __builtin_fma(r, __builtin_fma(-b, r, 1.0), r);
+  r = __builtin_fma(r, __builtin_fma(-b, r, 1.0), r);
+  const double t = __builtin_fma(-r, b, 1.0);
+  const double r2 = ieee_step(r, t);
+  const double t2 = __builtin_fma(-r2, b, 1.0);
+  return __builtin_fabs(t2) < __builtin_fabs(t) ? r2 : r;
+}
+
 __device__ __forceinline__ double cr_sqrt(double x) {
   const double s = __builtin_sqrt(x);
   const double t = __builtin_fma(-s, s, x);

@@ -65,7 +65,7 @@ template <typename R> struct Prim { R u, v, p, c; };
 __device__ __forceinline__ Prim<double> prim(double r, double mx, double my, double E,
                                              double gamma, double gm1) {
   Prim<double> w;
-  double rinv = cr_div(1.0, r);
+  double rinv = cr_rcp_pos(r);
   w.u = mx * rinv;
   w.v = my * rinv;
   double ke2 = mx * w.u + my * w.v;
@@ -739,7 +739,7 @@ __global__ __launch_bounds__(TX * TY) void stage_kernel(StageArgs a) {
     if (g.cyl) {
       const Prim<R>& w = wo;  // the cell's primitive variables (stage input)
       const double ri = g.xlo + ((double)I + 0.5) * g.dx;
-      const R ir = (R)cr_div(1.0, ri);
+      const R ir = (R)cr_rcp_pos(ri);
       S[0] = S[0] - ir * mx;
       S[1] = S[1] - ir * (mx * w.u);
       S[2] = S[2] - ir * (my * w.u);

@@ -90,4 +90,23 @@ __device__ __forceinline__ double cr_sqrt(double x) {
   return __builtin_fabs(t2) < __builtin_fabs(t) ? s2 : s;
 }
 
+// Correctly rounded square root of a positive normal x (squared sound
+// speeds): reciprocal square root, Goldschmidt refinement (g -> sqrt(x),
+// h -> 1 / (2 sqrt(x))) and two corrections, then the neighbour check; no
+// scaling or special-value steps.  (x <= 0 gives NaN, not the IEEE 0: such a
+// state is reported as unphysical anyway.)
+__device__ __forceinline__ double cr_sqrt_pos(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  const double e = __builtin_fma(-h, g, 0.5);
+  g = __builtin_fma(g, e, g);
+  h = __builtin_fma(h, e, h);
+  g = __builtin_fma(__builtin_fma(-g, g, x), h, g);
+  const double s = __builtin_fma(__builtin_fma(-g, g, x), h, g);
+  const double t = __builtin_fma(-s, s, x);
+  const double s2 = ieee_step(s, t);
+  const double t2 = __builtin_fma(-s2, s2, x);
+  return __builtin_fabs(t2) < __builtin_fabs(t) ? s2 : s;
+}
+
 }  // namespace hy

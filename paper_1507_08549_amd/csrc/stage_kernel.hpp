@@ -70,7 +70,7 @@ __device__ __forceinline__ Prim<double> prim(double r, double mx, double my, dou
   w.v = my * rinv;
   double ke2 = mx * w.u + my * w.v;
   w.p = gm1 * (E - 0.5 * ke2);
-  w.c = cr_sqrt((gamma * w.p) * rinv);
+  w.c = cr_sqrt_pos((gamma * w.p) * rinv);
   return w;
 }
 

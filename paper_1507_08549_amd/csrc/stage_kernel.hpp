@@ -133,7 +133,7 @@ __device__ __forceinline__ double weno5_face(double p0, double p1, double p2, do
   double np, dp, nm, dm;
   weno5_nd(p0, p1, p2, p3, p4, eps, np, dp);
   weno5_nd(m0, m1, m2, m3, m4, eps, nm, dm);
-  return cr_div_pos(np * dm + nm * dp, dp * dm);  // dp, dm > 0: sums of positive weights
+  return cr_div_pos_normal(np * dm + nm * dp, dp * dm);  // dp, dm > 0: sums of positive weights
 }
 
 __device__ __forceinline__ double lf_fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
@@ -154,17 +154,21 @@ __device__ __forceinline__ Prim<float> prim(float r, float mx, float my, float E
 }
 
 // Textbook weights a_k = d_k / s_k with hardware reciprocals (no overflow of
-// the products in single precision).
-__device__ __forceinline__ float weno5(float v0, float v1, float v2, float v3, float v4, float eps) {
-  const float c1312 = 13.0f / 12.0f;
-  float d = v0 - 2.0f * v1 + v2, e = v0 - 4.0f * v1 + 3.0f * v2;
-  float b0 = c1312 * d * d + 0.25f * e * e;
-  d = v1 - 2.0f * v2 + v3;
+// the products in single precision); t0..t2 are 13/12 times the squared
+// second differences of the three candidate stencils, which a run of faces
+// shares between neighbouring stencils.
+__device__ __forceinline__ float sq2_at(float l, float m, float r) {
+  const float d = l - 2.0f * m + r;
+  return (13.0f / 12.0f) * d * d;
+}
+__device__ __forceinline__ float weno5_t(float v0, float v1, float v2, float v3, float v4, float t0, float t1,
+                                         float t2, float eps) {
+  float e = v0 - 4.0f * v1 + 3.0f * v2;
+  float b0 = t0 + 0.25f * e * e;
   e = v1 - v3;
-  float b1 = c1312 * d * d + 0.25f * e * e;
-  d = v2 - 2.0f * v3 + v4;
+  float b1 = t1 + 0.25f * e * e;
   e = 3.0f * v2 - 4.0f * v3 + v4;
-  float b2 = c1312 * d * d + 0.25f * e * e;
+  float b2 = t2 + 0.25f * e * e;
   float s0 = eps + b0, s1 = eps + b1, s2 = eps + b2;
   float a0 = 0.1f * rcpf(s0 * s0);
   float a1 = 0.6f * rcpf(s1 * s1);
@@ -173,6 +177,10 @@ __device__ __forceinline__ float weno5(float v0, float v1, float v2, float v3, f
   float p1 = -v1 + 5.0f * v2 + 2.0f * v3;
   float p2 = 2.0f * v2 + 5.0f * v3 - v4;
   return (a0 * p0 + a1 * p1 + a2 * p2) * (rcpf(a0 + a1 + a2) * (1.0f / 6.0f));
+}
+
+__device__ __forceinline__ float weno5(float v0, float v1, float v2, float v3, float v4, float eps) {
+  return weno5_t(v0, v1, v2, v3, v4, sq2_at(v0, v1, v2), sq2_at(v1, v2, v3), sq2_at(v2, v3, v4), eps);
 }
 
 __device__ __forceinline__ float lf_fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
@@ -325,8 +333,24 @@ __device__ __forceinline__ void face_run(const R* P, const R* M, int st, R eps, 
       asm volatile("" : "+v"(out[j]) : : "memory");  // one face at a time: few live registers
     }
   } else {
+    // single precision: the squared second-difference terms shared the same way
+    R tp[NR + 3], tm[NR + 4];
 #pragma unroll
-    for (int j = 0; j < NR; ++j) out[j] = face_value(P + j * st, M + j * st, st, eps);
+    for (int j = 0; j < NR; ++j) {
+      if (j == 0) {
+        tp[1] = sq2_at(P[0], P[st], P[2 * st]);
+        tp[2] = sq2_at(P[st], P[2 * st], P[3 * st]);
+        tm[2] = sq2_at(M[3 * st], M[2 * st], M[st]);
+        tm[3] = sq2_at(M[4 * st], M[3 * st], M[2 * st]);
+      }
+      tp[j + 3] = sq2_at(P[(j + 2) * st], P[(j + 3) * st], P[(j + 4) * st]);
+      tm[j + 4] = sq2_at(M[(j + 5) * st], M[(j + 4) * st], M[(j + 3) * st]);
+      out[j] = weno5_t(P[j * st], P[(j + 1) * st], P[(j + 2) * st], P[(j + 3) * st], P[(j + 4) * st],
+                       tp[j + 1], tp[j + 2], tp[j + 3], eps) +
+               weno5_t(M[(j + 5) * st], M[(j + 4) * st], M[(j + 3) * st], M[(j + 2) * st], M[(j + 1) * st],
+                       tm[j + 4], tm[j + 3], tm[j + 2], eps);
+      asm volatile("" : "+v"(out[j]) : : "memory");
+    }
   }
 }
 

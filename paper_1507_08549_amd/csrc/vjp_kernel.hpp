@@ -45,9 +45,13 @@ __device__ __forceinline__ void weno5_adj(const double v[5], double eps, double 
   const double d0 = v[0] - 2.0 * v[1] + v[2], e0 = v[0] - 4.0 * v[1] + 3.0 * v[2];
   const double d1 = v[1] - 2.0 * v[2] + v[3], e1 = v[1] - v[3];
   const double d2 = v[2] - 2.0 * v[3] + v[4], e2 = 3.0 * v[2] - 4.0 * v[3] + v[4];
-  const double E0 = eps + (c1312 * d0 * d0 + 0.25 * e0 * e0);
-  const double E1 = eps + (c1312 * d1 * d1 + 0.25 * e1 * e1);
-  const double E2 = eps + (c1312 * d2 * d2 + 0.25 * e2 * e2);
+  // (13/12) d_k and e_k / 4 serve both beta_k and its derivative below
+  const double cd0 = c1312 * d0, qe0 = 0.25 * e0;
+  const double cd1 = c1312 * d1, qe1 = 0.25 * e1;
+  const double cd2 = c1312 * d2, qe2 = 0.25 * e2;
+  const double E0 = eps + (cd0 * d0 + qe0 * e0);
+  const double E1 = eps + (cd1 * d1 + qe1 * e1);
+  const double E2 = eps + (cd2 * d2 + qe2 * e2);
   const double s0 = E0 * E0, s1 = E1 * E1, s2 = E2 * E2;
   // weights over the common denominator; one division gives 1/sum(w) and 1/(E0 E1 E2)
   const double w0 = s1 * s2, w1 = 6.0 * (s0 * s2), w2 = 3.0 * (s0 * s1);
@@ -66,16 +70,17 @@ __device__ __forceinline__ void weno5_adj(const double v[5], double eps, double 
   const double Q1 = -v[1] + 5.0 * v[2] + 2.0 * v[3];
   const double Q2 = 2.0 * v[2] + 5.0 * v[3] - v[4];
   const double W6 = om0 * Q0 + om1 * Q1 + om2 * Q2;
-  // beta-adjoints -2 nu omega_k (q_k - W) / E_k, with 1 / E_k = (product of the other two) / P
-  const double f = (-1.0 / 3.0) * nu * iP;
+  // twice the beta-adjoints -2 nu omega_k (q_k - W) / E_k, with 1 / E_k =
+  // (product of the other two) / P; dbeta_k = 2 (13/12) d_k dd_k + 2 (e_k / 4) de_k
+  const double f = (-2.0 / 3.0) * nu * iP;
   const double bb0 = f * (om0 * (Q0 - W6)) * E12;
   const double bb1 = f * (om1 * (Q1 - W6)) * E02;
   const double bb2 = f * (om2 * (Q2 - W6)) * E01;
   const double n6 = nu * (1.0 / 6.0);
   const double c0 = n6 * om0, c1 = n6 * om1, c2 = n6 * om2;
-  const double t0 = bb0 * (13.0 / 6.0) * d0, h0 = bb0 * 0.5 * e0;
-  const double t1 = bb1 * (13.0 / 6.0) * d1, h1 = bb1 * 0.5 * e1;
-  const double t2 = bb2 * (13.0 / 6.0) * d2, h2 = bb2 * 0.5 * e2;
+  const double t0 = bb0 * cd0, h0 = bb0 * qe0;
+  const double t1 = bb1 * cd1, h1 = bb1 * qe1;
+  const double t2 = bb2 * cd2, h2 = bb2 * qe2;
   vb[0] = 2.0 * c0 + t0 + h0;
   vb[1] = -7.0 * c0 - c1 - 2.0 * t0 - 4.0 * h0 + t1 + h1;
   vb[2] = 11.0 * c0 + 5.0 * c1 + 2.0 * c2 + t0 + 3.0 * h0 - 2.0 * t1 + t2 + 3.0 * h2;
@@ -89,9 +94,12 @@ __device__ __forceinline__ void weno5_adj(const float v[5], float eps, float nu,
   const float d0 = v[0] - 2.0f * v[1] + v[2], e0 = v[0] - 4.0f * v[1] + 3.0f * v[2];
   const float d1 = v[1] - 2.0f * v[2] + v[3], e1 = v[1] - v[3];
   const float d2 = v[2] - 2.0f * v[3] + v[4], e2 = 3.0f * v[2] - 4.0f * v[3] + v[4];
-  const float r0 = rcpf(eps + (c1312 * d0 * d0 + 0.25f * e0 * e0));
-  const float r1 = rcpf(eps + (c1312 * d1 * d1 + 0.25f * e1 * e1));
-  const float r2 = rcpf(eps + (c1312 * d2 * d2 + 0.25f * e2 * e2));
+  const float cd0 = c1312 * d0, qe0 = 0.25f * e0;
+  const float cd1 = c1312 * d1, qe1 = 0.25f * e1;
+  const float cd2 = c1312 * d2, qe2 = 0.25f * e2;
+  const float r0 = rcpf(eps + (cd0 * d0 + qe0 * e0));
+  const float r1 = rcpf(eps + (cd1 * d1 + qe1 * e1));
+  const float r2 = rcpf(eps + (cd2 * d2 + qe2 * e2));
   const float a0 = 0.1f * r0 * r0, a1 = 0.6f * r1 * r1, a2 = 0.3f * r2 * r2;
   const float ia = rcpf(a0 + a1 + a2);
   const float om0 = a0 * ia, om1 = a1 * ia, om2 = a2 * ia;
@@ -99,13 +107,15 @@ __device__ __forceinline__ void weno5_adj(const float v[5], float eps, float nu,
   const float q1 = (-v[1] + 5.0f * v[2] + 2.0f * v[3]) * (1.0f / 6.0f);
   const float q2 = (2.0f * v[2] + 5.0f * v[3] - v[4]) * (1.0f / 6.0f);
   const float W = om0 * q0 + om1 * q1 + om2 * q2;
-  const float bb0 = -2.0f * nu * om0 * (q0 - W) * r0;
-  const float bb1 = -2.0f * nu * om1 * (q1 - W) * r1;
-  const float bb2 = -2.0f * nu * om2 * (q2 - W) * r2;
+  // twice the beta-adjoints (see the FP64 form)
+  const float f = -4.0f * nu;
+  const float bb0 = f * om0 * (q0 - W) * r0;
+  const float bb1 = f * om1 * (q1 - W) * r1;
+  const float bb2 = f * om2 * (q2 - W) * r2;
   const float c0 = nu * om0 * (1.0f / 6.0f), c1 = nu * om1 * (1.0f / 6.0f), c2 = nu * om2 * (1.0f / 6.0f);
-  const float t0 = bb0 * (13.0f / 6.0f) * d0, h0 = bb0 * 0.5f * e0;
-  const float t1 = bb1 * (13.0f / 6.0f) * d1, h1 = bb1 * 0.5f * e1;
-  const float t2 = bb2 * (13.0f / 6.0f) * d2, h2 = bb2 * 0.5f * e2;
+  const float t0 = bb0 * cd0, h0 = bb0 * qe0;
+  const float t1 = bb1 * cd1, h1 = bb1 * qe1;
+  const float t2 = bb2 * cd2, h2 = bb2 * qe2;
   vb[0] = 2.0f * c0 + t0 + h0;
   vb[1] = -7.0f * c0 - c1 - 2.0f * t0 - 4.0f * h0 + t1 + h1;
   vb[2] = 11.0f * c0 + 5.0f * c1 + 2.0f * c2 + t0 + 3.0f * h0 - 2.0f * t1 + t2 + 3.0f * h2;

@@ -275,7 +275,16 @@ __global__ __launch_bounds__(64 * NL) void vjp_line_kernel(VjpPass P) {
   auto gidx = [&](int along, int across) -> size_t {
     return DIR == 0 ? (size_t)across * g.nx + along : (size_t)along * g.nx + across;
   };
-  auto wrap = [&](int k) { return ((k % na) + na) % na; };
+  // ring index of point k: the points a line segment touches lie within one
+  // line length on either side once the line holds 64 cells or more, so one
+  // correction does; shorter rings take the remainder
+  auto wrap = [&](int k) {
+    if (na >= 64) {
+      k += k < 0 ? na : 0;
+      return k >= na ? k - na : k;
+    }
+    return ((k % na) + na) % na;
+  };
   // state of point k of line b (boundary conditions applied)
   auto load_state = [&](int k, int b, R u4[4]) {
     bool flip = false;

@@ -24,10 +24,11 @@
 //  ls_clear / ls_alpha   max|u|, max|v| of the corner velocity into 64
 //                        sub-slots (bit patterns of non-negative doubles order
 //                        like the values, so atomicMax on them is exact);
-//  ls_stage              one RK stage: 32 x 8 corner tile with a 3-corner halo
-//                        in LDS, the one-sided differences (times 1/spacing)
-//                        once per edge in LDS,
-//                        four reconstructions per corner;
+//  ls_stage              one RK stage: 32 x 16 corner tile with a 3-corner
+//                        halo in LDS (read without the ghost rule where the
+//                        halo lies inside the grid), the one-sided differences
+//                        (times 1/spacing) once per edge in LDS, four
+//                        reconstructions per corner;
 //  ls_front              front points, one work item per corner (its zero test,
 //                        its right edge, its upper edge), one atomic per
 //                        wavefront to reserve space (the order of the points is
@@ -49,7 +50,8 @@ namespace hy {
 
 namespace {
 
-constexpr int LTX = 32, LTY = 8;  // stage tile (corners)
+constexpr int LTX = 32, LTY = 16;  // stage tile (corners)
+constexpr int LST_THREADS = LTX * LTY;  // stage kernel: one work item per corner
 constexpr int LS_THREADS = 256;
 
 // Corner index along one axis with the ghost rule; returns the corner to read
@@ -89,6 +91,15 @@ __device__ __forceinline__ void read_amax(const LsCtl* lc, double* sh, double& m
   __syncthreads();
   mu = sh[0];
   mv = sh[1];
+}
+
+// WENO5-JS of the fluid (same weights and order) at the right face of v2; the
+// denominator is a sum of positive weights, at least 60 eps^4, so the
+// normal-denominator division gives the correctly rounded quotient.
+__device__ __forceinline__ double ls_weno5(double v0, double v1, double v2, double v3, double v4, double eps) {
+  double num, den;
+  weno5_nd(v0, v1, v2, v3, v4, eps, num, den);
+  return cr_div_pos_normal(num, den);
 }
 
 }  // namespace
@@ -131,7 +142,7 @@ __global__ __launch_bounds__(LS_THREADS) void ls_alpha_kernel(const double* vel,
   }
 }
 
-__global__ __launch_bounds__(LS_THREADS) void ls_stage_kernel(LsArgs a) {
+__global__ __launch_bounds__(LST_THREADS) void ls_stage_kernel(LsArgs a) {
   constexpr int PX = LTX + 6, PY = LTY + 6;
   __shared__ double T[PY][PX];
   __shared__ double QX[LTY][LTX + 5];
@@ -144,34 +155,46 @@ __global__ __launch_bounds__(LS_THREADS) void ls_stage_kernel(LsArgs a) {
   const int nx = a.mx - 1, ny = a.my - 1;
 
   // tile of S with a 3-corner halo; only the x halo of interior rows and the y
-  // halo of interior columns are used
-  for (int k = tid; k < PX * PY; k += LS_THREADS) {
-    const int ly = k / PX, lx = k % PX;
-    const int gi = i0 - 3 + lx, gj = j0 - 3 + ly;
-    const bool xin = gi >= 0 && gi <= nx, yin = gj >= 0 && gj <= ny;
-    double v = 0.0;
-    if (gi >= -3 && gi <= nx + 3 && gj >= -3 && gj <= ny + 3 && (xin || yin)) {
-      int ex, ey;
-      const int ci = ls_map(gi, nx, a.bc[0], a.bc[1], ex);
-      const int cj = ls_map(gj, ny, a.bc[2], a.bc[3], ey);
-      const double* V = a.V;
-      if (ex >= 0 && yin) {
-        const int cjj = ls_map(gj, ny, a.bc[2], a.bc[3], ey);
-        v = 2.0 * V[(size_t)cjj * a.mx + ex] - V[(size_t)cjj * a.mx + ci];
-      } else if (ey >= 0 && xin) {
-        v = 2.0 * V[(size_t)ey * a.mx + ci] - V[(size_t)cj * a.mx + ci];
-      } else if (ex < 0 && ey < 0) {
-        v = V[(size_t)cj * a.mx + ci];
-      }
+  // halo of interior columns are used.  A tile whose halo lies inside the
+  // grid (and off a periodic image row or column) reads every corner as
+  // itself.
+  const bool interior = i0 >= 3 && j0 >= 3 && i0 + LTX + 2 <= nx - (a.bc[1] == 0 ? 1 : 0) &&
+                        j0 + LTY + 2 <= ny - (a.bc[3] == 0 ? 1 : 0);
+  if (interior) {
+    const double* V = a.V + ((size_t)(j0 - 3) * a.mx + (i0 - 3));
+    for (int k = tid; k < PX * PY; k += LST_THREADS) {
+      const int ly = k / PX, lx = k - ly * PX;
+      T[ly][lx] = V[(size_t)ly * a.mx + lx];
     }
-    T[ly][lx] = v;
+  } else {
+    for (int k = tid; k < PX * PY; k += LST_THREADS) {
+      const int ly = k / PX, lx = k % PX;
+      const int gi = i0 - 3 + lx, gj = j0 - 3 + ly;
+      const bool xin = gi >= 0 && gi <= nx, yin = gj >= 0 && gj <= ny;
+      double v = 0.0;
+      if (gi >= -3 && gi <= nx + 3 && gj >= -3 && gj <= ny + 3 && (xin || yin)) {
+        int ex, ey;
+        const int ci = ls_map(gi, nx, a.bc[0], a.bc[1], ex);
+        const int cj = ls_map(gj, ny, a.bc[2], a.bc[3], ey);
+        const double* V = a.V;
+        if (ex >= 0 && yin) {
+          const int cjj = ls_map(gj, ny, a.bc[2], a.bc[3], ey);
+          v = 2.0 * V[(size_t)cjj * a.mx + ex] - V[(size_t)cjj * a.mx + ci];
+        } else if (ey >= 0 && xin) {
+          v = 2.0 * V[(size_t)ey * a.mx + ci] - V[(size_t)cj * a.mx + ci];
+        } else if (ex < 0 && ey < 0) {
+          v = V[(size_t)cj * a.mx + ci];
+        }
+      }
+      T[ly][lx] = v;
+    }
   }
   __syncthreads();
-  for (int k = tid; k < LTY * (LTX + 5); k += LS_THREADS) {
+  for (int k = tid; k < LTY * (LTX + 5); k += LST_THREADS) {
     const int r = k / (LTX + 5), e = k % (LTX + 5);
     QX[r][e] = (T[r + 3][e + 1] - T[r + 3][e]) * a.idx;
   }
-  for (int k = tid; k < (LTY + 5) * LTX; k += LS_THREADS) {
+  for (int k = tid; k < (LTY + 5) * LTX; k += LST_THREADS) {
     const int e = k / LTX, c = k % LTX;
     QY[e][c] = (T[e + 1][c + 3] - T[e][c + 3]) * a.idy;
   }
@@ -183,10 +206,10 @@ __global__ __launch_bounds__(LS_THREADS) void ls_stage_kernel(LsArgs a) {
   const int i = i0 + tx, j = j0 + ty;
   if (i > nx || j > ny) return;
   const double* qx = &QX[ty][tx];
-  const double pm = weno5(qx[0], qx[1], qx[2], qx[3], qx[4], a.eps);
-  const double pp = weno5(qx[5], qx[4], qx[3], qx[2], qx[1], a.eps);
-  const double qm = weno5(QY[ty][tx], QY[ty + 1][tx], QY[ty + 2][tx], QY[ty + 3][tx], QY[ty + 4][tx], a.eps);
-  const double qp = weno5(QY[ty + 5][tx], QY[ty + 4][tx], QY[ty + 3][tx], QY[ty + 2][tx], QY[ty + 1][tx], a.eps);
+  const double pm = ls_weno5(qx[0], qx[1], qx[2], qx[3], qx[4], a.eps);
+  const double pp = ls_weno5(qx[5], qx[4], qx[3], qx[2], qx[1], a.eps);
+  const double qm = ls_weno5(QY[ty][tx], QY[ty + 1][tx], QY[ty + 2][tx], QY[ty + 3][tx], QY[ty + 4][tx], a.eps);
+  const double qp = ls_weno5(QY[ty + 5][tx], QY[ty + 4][tx], QY[ty + 3][tx], QY[ty + 2][tx], QY[ty + 1][tx], a.eps);
   // a periodic image corner is computed as corner 0 (same stencil, same
   // velocity and stage input; the step input holds the images already, see
   // ls_images_kernel, so its own S0 is corner 0's and W may alias S0)
@@ -432,7 +455,7 @@ hipError_t launch_ls_images(const LsArgs& a, double* S, hipStream_t s) {
 
 hipError_t launch_ls_stage(const LsArgs& a, hipStream_t s) {
   const int nb = ((a.mx + LTX - 1) / LTX) * ((a.my + LTY - 1) / LTY);
-  hipLaunchKernelGGL(ls_stage_kernel, dim3(nb), dim3(LS_THREADS), 0, s, a);
+  hipLaunchKernelGGL(ls_stage_kernel, dim3(nb), dim3(LST_THREADS), 0, s, a);
   return hipGetLastError();
 }
 

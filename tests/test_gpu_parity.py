@@ -62,7 +62,7 @@ def _assert_same(got, want, what):
 BCS = [[P, P, P, P], [T, T, T, T], [R, R, R, R], [R, T, R, T], [T, R, P, P]]
 # (a cylindrical grid's axis is reflecting, never periodic)
 BC_GEOMETRY = [(bc, geo) for geo in (0, 1) for bc in BCS if not (geo == 1 and bc[0] == P)]
-SHAPES = [(8, 8), (11, 13), (16, 16), (17, 33), (70, 40)]
+SHAPES = [(3, 3), (3, 5), (8, 8), (11, 13), (16, 16), (17, 33), (70, 40)]  # (3, 3): the smallest 2D grid
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: f"{s[0]}x{s[1]}")

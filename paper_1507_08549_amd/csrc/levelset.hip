@@ -302,8 +302,8 @@ __global__ __launch_bounds__(LS_THREADS) void ls_front_kernel(LsArgs a, double* 
   }
 }
 
-// Distance and blend.  Corner tile 64 x 16 (four corners per work item, rows
-// ty, ty+4, ty+8, ty+12); points staged through LDS in chunks.
+// Distance and blend.  Corner tile 32 x 16 (two corners per work item, rows
+// ty and ty + 8); points staged through LDS in chunks.
 constexpr int DTX = 32, DTY = 16, DCH = 512;
 constexpr int DRS = LS_THREADS / DTX;  // row stride of a work item's corners
 constexpr int DR = DTY / DRS;          // corners per work item

@@ -13,8 +13,8 @@ the oracle's state, so the FP32-bulk form's relative L1 density error against
 the FP64 path at a checkpoint is its error against the oracle there.
 
 FP32-bulk bounds (about three times the largest error measured over the run):
-shear layer 5e-6 (1.5e-6 after 2000 steps), heavy-over-light layer 1.5e-6
-(4.9e-7 after 5000), polytrope 2.5e-6 (7.2e-7 after 1000).  The oracle's own
+shear layer 5e-6 (1.4e-6 after 2000 steps), heavy-over-light layer 1.5e-6
+(5.4e-7 after 5000), polytrope 2.5e-6 (7.7e-7 after 1000).  The oracle's own
 growth of an initial difference of FP32 size over the same runs (the
 initial state rounded to FP32, in the digest file) is printed beside them.
 """

@@ -38,22 +38,12 @@ __device__ __forceinline__ double cr_div(double a, double b) {
   return __builtin_fabs(t2) < __builtin_fabs(t) ? q2 : q;
 }
 
-// The same for a divisor known to be positive: the true quotient then lies on
-// the side of sign(t) alone.
-__device__ __forceinline__ double cr_div_pos(double a, double b) {
-  const double q = a / b;
-  const double t = __builtin_fma(-q, b, a);
-  const double q2 = ieee_step(q, t);
-  const double t2 = __builtin_fma(-q2, b, a);
-  return __builtin_fabs(t2) < __builtin_fabs(t) ? q2 : q;
-}
-
-// cr_div_pos for a quotient of a positive normal denominator whose
-// reciprocal is normal and a quotient that is zero or normal: the faithful
-// quotient from the hardware reciprocal refined by two Newton steps and one
-// correction step (q0 = a r, q = q0 + (a - q0 b) r), without the scaling and
-// special-value steps of the general division sequence, then the same
-// neighbour check.  The WENO face values are such quotients: their
+// cr_div for a positive normal denominator whose reciprocal is normal and a
+// quotient that is zero or normal: the faithful quotient from the hardware
+// reciprocal refined by two Newton steps and one correction step (q0 = a r,
+// q = q0 + (a - q0 b) r), without the scaling and special-value steps of the
+// general division sequence, then the same neighbour check (with b > 0 the
+// true quotient lies on the side of sign(t) alone).  The WENO face values are such quotients: their
 // denominators, products of sums of weights, lie between about 3e-47
 // (eps = 1e-6) and the overflow of the numerator that comes with them.
 __device__ __forceinline__ double cr_div_pos_normal(double a, double b) {

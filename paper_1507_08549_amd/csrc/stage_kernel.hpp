@@ -7,8 +7,10 @@
 // without touching HBM again until the store:
 //   1. primitive variables and the globally Lax-Friedrichs split fluxes
 //      f+- = (F(U) +- alpha_x U) / 2 of every x-point (Sect. 2.1),
-//   2. WENO5 reconstruction at every x-face of the tile, one (face, component)
-//      per work item: F^ = W(f+ upwind-left) + W(f- upwind-right); with the
+//   2. WENO5 reconstruction at every x-face of the tile, a run of four
+//      consecutive faces of one component per work item (the runs share the
+//      stencils' second differences; the last face of every row is a task of
+//      its own): F^ = W(f+ upwind-left) + W(f- upwind-right); with the
 //      characteristic option one whole face per work item (char_face),
 //   3. the same in y with alpha_y (skipped in the 1D limit),
 //   4. per cell: divergence, sources of Eq. euler2D (gravity, cylindrical
@@ -114,13 +116,6 @@ __device__ __forceinline__ void weno5_nd_d2(double v0, double v1, double v2, dou
 __device__ __forceinline__ void weno5_nd(double v0, double v1, double v2, double v3, double v4, double eps,
                                          double& num, double& den) {
   weno5_nd_d2(v0, v1, v2, v3, v4, d2_at(v0, v1, v2), d2_at(v1, v2, v3), d2_at(v2, v3, v4), eps, num, den);
-}
-
-__device__ __forceinline__ double weno5(double v0, double v1, double v2, double v3, double v4,
-                                        double eps) {
-  double num, den;
-  weno5_nd(v0, v1, v2, v3, v4, eps, num, den);
-  return cr_div(num, den);
 }
 
 // Face value of a split flux: left-biased reconstruction of the f+ stencil

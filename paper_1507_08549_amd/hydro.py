@@ -66,7 +66,8 @@ ENTRY_POINTS = ("hydro_create", "hydro_destroy", "hydro_cfl", "hydro_step", "hyd
 
 def declared_entry_points(header: str = HEADER):
     """Function names declared in the public header (for the ABI tests)."""
-    src = open(header).read()
+    with open(header) as f:
+        src = f.read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(hydro_[a-z_]+)\s*\(", src)))
 

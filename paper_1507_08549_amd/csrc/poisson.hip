@@ -180,8 +180,6 @@ __global__ __launch_bounds__(NT) void poisson_block_kernel(PoissonArgs a) {
 
   const int ti1 = min(i0 + TX, nr) - 1, tj1 = min(j0 + TY, nz) - 1;  // owned cells (inclusive)
   const int ox = i0 - H, oy = j0 - H;  // tile origin of the LDS arrays
-  const int tr = tid / 32, tm = tid % 32;
-  constexpr int MW = (HX + 31) / 32;
   double change = 0.0;
   for (int h = 0; h < 2 * kk; ++h) {
     const int c = h & 1;
@@ -189,30 +187,28 @@ __global__ __launch_bounds__(NT) void poisson_block_kernel(PoissonArgs a) {
     const int lxa = max(i0 - g, 0) - ox, lxb = min(ti1 + g, nr - 1) - ox;
     const int lya = max(j0 - g, 0) - oy, lyb = min(tj1 + g, nz - 1) - oy;
     const double(*Q)[HX] = PC[1 - c];
-    for (int ly = lya + tr; ly <= lyb; ly += NT / 32) {
+    // the (row, colour slot) pairs of the active rows, dealt to the work items
+    // in order (the cells of one colour are independent of each other)
+    const int nslot = (lyb - lya + 1) * HX;
+    for (int idx = tid; idx < nslot; idx += NT) {
+      const int ry = idx / HX, m = idx - ry * HX;
+      const int ly = lya + ry;
       const int o = (c + ly) & 1;  // cells of colour c in this row: lx = 2m + o
-      const int mlo = (lxa - o + 1) >> 1, mhi = (lxb - o) >> 1;
+      if (2 * m + o < lxa || 2 * m + o > lxb) continue;
       const int j = oy + ly;
       const double aS = j > 0 ? a.idz2 : 0.0;
-      const double* ID = cID[j > 0 ? 1 : 0];
-      // up to MW cells of the row per work item, independent of each other
-#pragma unroll
-      for (int w = 0; w < MW; ++w) {
-        const int m = mlo + tm + 32 * w;
-        if (m > mhi) continue;
-        const int lx = 2 * m + o;
-        const double aE = cAE[lx], aW = cAW[lx], aN = a.idz2;
-        const double pE = Q[ly][m + o], pW = Q[ly][m + o - 1];
-        const double pN = Q[ly + 1][m], pS = Q[ly - 1][m];
-        const double num = (((aE * pE + aW * pW) + aN * pN) + aS * pS) - a.four_pi_g * RC[c][ly][m];
-        const double gs = num * ID[lx];
-        const double old = PC[c][ly][m];
-        const double nw = old + a.omega * (gs - old);
-        PC[c][ly][m] = nw;
-        const int i = ox + lx;
-        if (i >= i0 && i <= ti1 && j >= j0 && j <= tj1)
-          change = __builtin_fmax(change, nw == old ? 0.0 : cr_div(__builtin_fabs(nw - old), __builtin_fabs(nw)));
-      }
+      const int lx = 2 * m + o;
+      const double aE = cAE[lx], aW = cAW[lx], aN = a.idz2;
+      const double pE = Q[ly][m + o], pW = Q[ly][m + o - 1];
+      const double pN = Q[ly + 1][m], pS = Q[ly - 1][m];
+      const double num = (((aE * pE + aW * pW) + aN * pN) + aS * pS) - a.four_pi_g * RC[c][ly][m];
+      const double gs = num * cID[j > 0 ? 1 : 0][lx];
+      const double old = PC[c][ly][m];
+      const double nw = old + a.omega * (gs - old);
+      PC[c][ly][m] = nw;
+      const int i = ox + lx;
+      if (i >= i0 && i <= ti1 && j >= j0 && j <= tj1)
+        change = __builtin_fmax(change, nw == old ? 0.0 : cr_div(__builtin_fabs(nw - old), __builtin_fabs(nw)));
     }
     __syncthreads();
     if (c == 1 && !redo) {

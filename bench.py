@@ -86,9 +86,9 @@ STAGE_COUNTERS = {
 # The potential solver's launch (4 iterations): measured HBM bytes and VALU
 # instructions (profiles/poisson_block_polytrope1024.md).
 POISSON_COUNTERS = {"sources": ["paper_1507_08549_amd/csrc/poisson.hip"],
-                    "sha256": "95ec086e5748981e710e82542427ad733d2f838d6e83560e48e50666d0a97e44", "iterations_per_launch": 4,
-                    "bytes_per_launch": 18.66e6 + 8.27e6, "valu_insts_per_launch": 9097838,
-                    "launch_us": 28.46}
+                    "sha256": "c48f737c8cdd706a942694d626cff0899aa68d4c680dc421ecbb8406d5215aa6", "iterations_per_launch": 4,
+                    "bytes_per_launch": 18.63e6 + 8.27e6, "valu_insts_per_launch": 9065717,
+                    "launch_us": 28.08}
 
 
 def sources_digest(files):

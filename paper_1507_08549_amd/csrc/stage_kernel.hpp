@@ -234,15 +234,17 @@ __device__ __forceinline__ bool char_face(const double* F, const double* Q, int 
   const double nl = Q[(1 + DIR) * np + il], nr = Q[(1 + DIR) * np + ir];
   const double tl = Q[(2 - DIR) * np + il], tr = Q[(2 - DIR) * np + ir];
   const double Hl = Q[3 * np + il], Hr = Q[3 * np + ir];
+  // (sqrt(rho) of two positive densities: den is a positive normal number;
+  // for a face with c2 <= 0, reported as unphysical, the values are not used)
   const double den = sl + sr;
-  const double un = cr_div(sl * nl + sr * nr, den);
-  const double ut = cr_div(sl * tl + sr * tr, den);
-  const double H = cr_div(sl * Hl + sr * Hr, den);
+  const double un = cr_div_pos_normal(sl * nl + sr * nr, den);
+  const double ut = cr_div_pos_normal(sl * tl + sr * tr, den);
+  const double H = cr_div_pos_normal(sl * Hl + sr * Hr, den);
   const double q2 = un * un + ut * ut;
   const double c2 = gm1 * (H - 0.5 * q2);
   const bool ok = c2 > 0.0 && __builtin_isfinite(c2);
-  const double c = cr_sqrt(c2), ic = cr_div(1.0, c);
-  const double b1 = cr_div(gm1, c2), b2 = (0.5 * q2) * b1;
+  const double c = cr_sqrt_pos(c2), ic = cr_rcp_pos(c);
+  const double b1 = cr_div_pos_normal(gm1, c2), b2 = (0.5 * q2) * b1;
   double gh[4];
 #pragma unroll
   for (int m = 0; m < 4; ++m) {

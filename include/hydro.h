@@ -285,8 +285,8 @@ int hydro_ls_front(hydro_ctx* ctx, const double* S, double* pts, int64_t cap, in
  * within about two spacings of the front are kept, far values become the
  * distance.  With no front point S is left as it is.  dist: NULL or device
  * [ny+1][nx+1] receiving d (untouched without front points).  *npoints (may be
- * NULL) receives the number of front points.  Synchronises once (to size the
- * search), then runs asynchronously. */
+ * NULL) receives the number of front points: then the call synchronises at
+ * its end; with npoints NULL it only enqueues. */
 int hydro_ls_redistance(hydro_ctx* ctx, double* S, double* dist, int64_t* npoints);
 
 /* Conserved totals: the integrals of rho, m_x, m_y and E over the grid, i.e.

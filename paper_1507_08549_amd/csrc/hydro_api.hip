@@ -764,14 +764,19 @@ int hydro_ls_front(hydro_ctx* c, const double* S, double* pts, int64_t cap, int6
 int hydro_ls_redistance(hydro_ctx* c, double* S, double* dist, int64_t* npoints) {
   HY_LS_PROLOGUE(c);
   if (!S) return HYDRO_E_INVALID;
-  long long np = 0;
-  if (int rc = ls_front(c, S, &np)) return rc;
-  if (np > 0) {
-    hy::LsArgs a = ls_args(c);
-    a.W = S;
-    HY_CHECK(hy::launch_ls_distance(a, c->ls_pts, dist, c->stream));
+  // the distance kernel reads the point count on the device (and leaves S and
+  // dist as they are when it is 0), so nothing waits between the two launches
+  hy::LsArgs a = ls_args(c);
+  a.V = S;
+  HY_CHECK(hy::launch_ls_front(a, c->ls_pts, c->stream));
+  a.W = S;
+  HY_CHECK(hy::launch_ls_distance(a, c->ls_pts, dist, c->stream));
+  if (npoints) {
+    HY_CHECK(hipMemcpyAsync(c->h_npts, &c->ls_ctl->npts, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                            c->stream));
+    HY_CHECK(hipStreamSynchronize(c->stream));
+    *npoints = (int64_t)*c->h_npts;
   }
-  if (npoints) *npoints = np;
   return HYDRO_OK;
 }
 

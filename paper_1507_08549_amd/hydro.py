@@ -387,14 +387,15 @@ class Solver:
         self._check(rc, "hydro_ls_front")
         return pts[:min(n.value, cap)]
 
-    def ls_redistance(self, S, dist=None):
-        """Re-distance S in place; returns the number of front points."""
+    def ls_redistance(self, S, dist=None, count=True):
+        """Re-distance S in place; returns the number of front points (count=True,
+        which waits for the result) or None (count=False: only enqueued)."""
         n = ctypes.c_int64()
         rc = self._lib.hydro_ls_redistance(self._h, self._corner(S, "S"),
                                            None if dist is None else self._corner(dist, "dist"),
-                                           ctypes.byref(n))
+                                           ctypes.byref(n) if count else None)
         self._check(rc, "hydro_ls_redistance")
-        return n.value
+        return n.value if count else None
 
     def sums(self, U):
         out = (ctypes.c_double * 4)()

@@ -142,6 +142,29 @@ def test_ls_redistance_without_front(torch, hydro):
         s.close()
 
 
+def test_ls_redistance_without_count_enqueues_the_same_work(torch, hydro):
+    """With npoints NULL the call only enqueues (the distance kernel reads the
+    point count on the device): the same field and distances as with the
+    count, and nothing changes without a front."""
+    prm = inputs.make_params(64, 64, 0.0, 1.0, 0.0, 1.0, [T, T, T, T], 1.4)
+    S, _ = _field(prm, 8)
+    flat = 1.0 + np.random.default_rng(2).uniform(0, 1, (65, 65))
+    s = hydro.Solver(prm)
+    try:
+        A, B, C = _dev(torch, S), _dev(torch, S), _dev(torch, flat)
+        dA, dB, dC = torch.zeros_like(A), torch.zeros_like(B), torch.full_like(C, -1.0)
+        assert s.ls_redistance(A, dA) > 0
+        assert s.ls_redistance(B, dB, count=False) is None
+        assert s.ls_redistance(C, dC, count=False) is None
+        torch.cuda.synchronize()
+        _same(B.cpu().numpy(), A.cpu().numpy(), "S")
+        _same(dB.cpu().numpy(), dA.cpu().numpy(), "distance")
+        _same(C.cpu().numpy(), flat, "S without a front")
+        assert bool((dC == -1.0).all())
+    finally:
+        s.close()
+
+
 def test_ls_periodic_images_from_inconsistent_input(torch, hydro, oracle_mod):
     prm = inputs.make_params(24, 16, 0.0, 1.0, 0.0, 1.0, [P, P, P, P], 1.4)
     S, vel = _field(prm, 5)

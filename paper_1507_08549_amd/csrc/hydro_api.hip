@@ -1,4 +1,4 @@
-// hydro_api.cpp -- the C ABI declared in include/hydro.h: context management,
+// hydro_api.hip -- the C ABI declared in include/hydro.h: context management,
 // parameter checks, and the launch sequences of the forward step, the
 // multi-step run with a device-side CFL step, the spatial operator, the
 // reductions and the discrete adjoint.

@@ -121,7 +121,9 @@ typedef struct hydro_ctx hydro_ctx;
  *           (g_x, g_y) per cell; borrowed, must outlive the context.
  *  stream   a hipStream_t, or NULL for the null stream.
  *  out      receives the context.
- * Allocates 7 state-sized scratch buffers.  Errors: INVALID, NOMEM, DEVICE. */
+ * Allocates 2 state-sized scratch buffers (64 B per cell); the first
+ * hydro_step_vjp_saved call adds 3 more, the first hydro_step_vjp call 5.
+ * Errors: INVALID, NOMEM, DEVICE. */
 int hydro_create(const hydro_params* params, const double* gravity, void* stream,
                  hydro_ctx** out);
 
@@ -200,7 +202,8 @@ int hydro_rhs(hydro_ctx* ctx, const double* V, double ax, double ay, double* L);
  * held fixed.  Recomputes the two intermediate stage states from U_n.
  * U_n, lam_next: device [4][ny][nx], read only; lam_prev: device
  * [4][ny][nx], overwritten (may not alias the others).  The atmosphere
- * floors must be disabled (INVALID otherwise).  Asynchronous. */
+ * floors must be disabled (INVALID otherwise).  The first adjoint call of a
+ * context allocates its adjoint scratch (NOMEM if that fails).  Asynchronous. */
 int hydro_step_vjp(hydro_ctx* ctx, const double* U_n, double dt, const hydro_alpha* alpha,
                    const double* lam_next, double* lam_prev);
 

@@ -21,7 +21,7 @@ struct hydro_ctx {
   size_t n;              // cells
   double* U1;            // stage states
   double* U2;
-  double* X[5];          // adjoint scratch: recomputed stage states, stage adjoints, partial sums
+  double* X[5];          // adjoint scratch (first adjoint call): recomputed stage states, stage adjoints, partial sum
   hy::Ctl* ctl;          // device control block
   double* rec;           // device: alpha record of hydro_step ([6])
   double* partial;       // device: per-block partial sums
@@ -187,6 +187,22 @@ int step_impl(hydro_ctx* c, const double* U_in, double* U_out, double dt, const 
   return HYDRO_OK;
 }
 
+// The adjoint's scratch, allocated by the first adjoint call: the two stage
+// adjoints and the y pass's partial sum (X[2..4]), and with recompute the two
+// recomputed stage states (X[0..1]).  Forward-only contexts never hold it.
+int ensure_adj(hydro_ctx* c, bool recompute) {
+  const size_t bytes = 4 * c->n * sizeof(double);
+  for (int k = recompute ? 0 : 2; k < 5; ++k) {
+    if (c->X[k]) continue;
+    if (hipMalloc(&c->X[k], bytes) != hipSuccess) {
+      c->X[k] = nullptr;
+      (void)hipGetLastError();
+      return HYDRO_E_NOMEM;
+    }
+  }
+  return HYDRO_OK;
+}
+
 // Adjoint of one step given its two stage states R1, R2.
 int vjp_impl(hydro_ctx* c, const double* U_n, const double* R1, const double* R2, double dt,
              const hydro_alpha* alpha, const double* lam_next, double* lam_prev) {
@@ -312,7 +328,6 @@ int hydro_create(const hydro_params* params, const double* gravity, void* stream
   const size_t bytes = 4 * c->n * sizeof(double);
   c->nsum = hy::sums_blocks(c->g);
   bool ok = hipMalloc(&c->U1, bytes) == hipSuccess && hipMalloc(&c->U2, bytes) == hipSuccess;
-  for (int k = 0; k < 5 && ok; ++k) ok = hipMalloc(&c->X[k], bytes) == hipSuccess;
   ok = ok && hipMalloc(&c->ctl, sizeof(hy::Ctl)) == hipSuccess;
   ok = ok && hipMalloc(&c->rec, 8 * sizeof(double)) == hipSuccess;
   ok = ok && hipMalloc(&c->partial, (size_t)c->nsum * 8 * sizeof(double)) == hipSuccess;
@@ -512,6 +527,7 @@ int hydro_step_vjp(hydro_ctx* c, const double* U_n, double dt, const hydro_alpha
   if (c->g.floor_on || c->g.charw) return HYDRO_E_INVALID;
   DeviceGuard dg(c->device);
   if (!dg.ok) return HYDRO_E_DEVICE;
+  if (int rc = ensure_adj(c, true)) return rc;
   // Recompute the stage states with the recorded speeds.
   double* R1 = c->X[0];
   double* R2 = c->X[1];
@@ -542,6 +558,7 @@ int hydro_step_vjp_saved(hydro_ctx* c, const double* U_n, const double* U1, cons
   if (c->g.floor_on || c->g.charw) return HYDRO_E_INVALID;
   DeviceGuard dg(c->device);
   if (!dg.ok) return HYDRO_E_DEVICE;
+  if (int rc = ensure_adj(c, false)) return rc;
   return vjp_impl(c, U_n, U1, U2, dt, alpha, lam_next, lam_prev);
 }
 

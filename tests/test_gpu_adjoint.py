@@ -413,3 +413,41 @@ def test_checkpointed_rollout_backward_twice(torch, hydro):
     (g0,) = torch.autograd.grad(
         _objective(torch, rollout(inputs.kh_sine_state(b, prm), s, steps, ckpt_every=None), prm), b)
     assert torch.equal(g1, g2) and torch.equal(g1, g0)
+
+
+def test_adjoint_scratch_is_allocated_by_the_first_adjoint_call(torch, hydro):
+    """A context holds two state-sized buffers; the first hydro_step_vjp_saved
+    call adds three (stage adjoints, partial sum), the first hydro_step_vjp two
+    more (recomputed stage states), later calls none; the results equal those
+    of a context whose scratch was already there."""
+    n = 1024
+    prm, U0 = inputs.kelvin_helmholtz(n)
+    state = 4 * n * n * 8
+    rng = np.random.default_rng(4)
+    U, lam = _dev(torch, U0), _dev(torch, rng.standard_normal(U0.shape))
+    U1, U2, Un = torch.empty_like(U), torch.empty_like(U), torch.empty_like(U)
+    out_a, out_b = torch.empty_like(U), torch.empty_like(U)
+    free = lambda: (torch.cuda.synchronize(), torch.cuda.mem_get_info()[0])[1]
+    f0 = free()
+    s = hydro.Solver(prm)
+    f1 = free()
+    print(f"ADJ scratch: create {(f0 - f1) / state:.2f} states", flush=True)
+    assert 1.9 * state <= f0 - f1 <= 2.3 * state
+    dt = 0.2 * s.cfl(U)
+    al = np.array([[3.0, 2.5], [3.1, 2.6], [3.2, 2.7]])
+    s.step_save(U, dt, al, U1, U2, out=Un)
+    f2 = free()
+    s.step_vjp_saved(U, U1, U2, dt, al, lam, out=out_a)
+    f3 = free()
+    s.step_vjp(U, dt, al, lam, out=out_b)
+    f4 = free()
+    s.step_vjp_saved(U, U1, U2, dt, al, lam, out=out_a)
+    s.step_vjp(U, dt, al, lam, out=out_b)
+    f5 = free()
+    print(f"ADJ scratch: first saved-state adjoint {(f2 - f3) / state:.2f}, "
+          f"first recomputing adjoint {(f3 - f4) / state:.2f}, later {(f4 - f5) / state:.2f} states", flush=True)
+    assert 2.7 * state <= f2 - f3 <= 3.3 * state
+    assert 1.9 * state <= f3 - f4 <= 2.3 * state
+    assert abs(f4 - f5) < 0.1 * state
+    assert torch.equal(out_a, out_b)
+    s.close()

@@ -37,6 +37,7 @@ struct hydro_ctx {
   double* ls_pts;        // front points, capacity 3 per corner ([2] each)
   hy::LsCtl* ls_ctl;
   unsigned long long* h_npts;  // pinned host staging
+  int ls_aset, ls_pset;  // the control sets the next advection step / front search use
   // potential solver (allocated by the first call)
   double* p_scratch;     // second potential buffer
   hy::PoissonCtl* pc;
@@ -694,6 +695,8 @@ int ensure_ls(hydro_ctx* c) {
     return HYDRO_E_NOMEM;
   }
   c->ls_ctl = lc;
+  c->ls_aset = c->ls_pset = 0;
+  HY_CHECK(hy::launch_ls_init(lc, c->stream));
   return HYDRO_OK;
 }
 
@@ -717,9 +720,11 @@ hy::LsArgs ls_args(const hydro_ctx* c) {
 int ls_front(hydro_ctx* c, const double* S, long long* np) {
   hy::LsArgs a = ls_args(c);
   a.V = S;
+  a.set = c->ls_pset;
+  c->ls_pset ^= 1;
   HY_CHECK(hy::launch_ls_front(a, c->ls_pts, c->stream));
-  HY_CHECK(hipMemcpyAsync(c->h_npts, &c->ls_ctl->npts, sizeof(unsigned long long), hipMemcpyDeviceToHost,
-                          c->stream));
+  HY_CHECK(hipMemcpyAsync(c->h_npts, &c->ls_ctl->npts[a.set], sizeof(unsigned long long),
+                          hipMemcpyDeviceToHost, c->stream));
   HY_CHECK(hipStreamSynchronize(c->stream));
   *np = (long long)*c->h_npts;
   return HYDRO_OK;
@@ -751,6 +756,8 @@ int hydro_ls_step(hydro_ctx* c, double* S, const double* vel, double s_flame, do
   a.s_f = s_flame;
   a.dt = dt;
   a.S0 = S;
+  a.set = c->ls_aset;
+  c->ls_aset ^= 1;
   HY_CHECK(hy::launch_ls_images(a, S, c->stream));
   HY_CHECK(hy::launch_ls_alpha(a, c->stream));
   const double b[3] = {1.0, 0.25, 2.0 / 3.0};
@@ -785,12 +792,14 @@ int hydro_ls_redistance(hydro_ctx* c, double* S, double* dist, int64_t* npoints)
   // dist as they are when it is 0), so nothing waits between the two launches
   hy::LsArgs a = ls_args(c);
   a.V = S;
+  a.set = c->ls_pset;
+  c->ls_pset ^= 1;
   HY_CHECK(hy::launch_ls_front(a, c->ls_pts, c->stream));
   a.W = S;
   HY_CHECK(hy::launch_ls_distance(a, c->ls_pts, dist, c->stream));
   if (npoints) {
-    HY_CHECK(hipMemcpyAsync(c->h_npts, &c->ls_ctl->npts, sizeof(unsigned long long), hipMemcpyDeviceToHost,
-                            c->stream));
+    HY_CHECK(hipMemcpyAsync(c->h_npts, &c->ls_ctl->npts[a.set], sizeof(unsigned long long),
+                            hipMemcpyDeviceToHost, c->stream));
     HY_CHECK(hipStreamSynchronize(c->stream));
     *npoints = (int64_t)*c->h_npts;
   }

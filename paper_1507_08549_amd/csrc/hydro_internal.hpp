@@ -123,11 +123,14 @@ int poisson_block_k(int config);
 int poisson_block_config(int nr, int nz);
 hipError_t launch_gravity(const PoissonArgs& a, double* g, hipStream_t s);
 
-// Level set on the corners ([ny+1][nx+1]).
+// Level set on the corners ([ny+1][nx+1]).  The point count and the speed
+// sub-slots come in two sets that alternate between calls: a call works in
+// one set and clears the other for the next call (stream order puts every use
+// of a set before that clear), so no call needs a clearing launch.
 struct LsCtl {
-  unsigned long long npts;  // front points found
-  unsigned long long pad[15];
-  unsigned long long amax[NSUB][16];  // [sub][0]: max|u|, [sub][1]: max|v| (bit patterns)
+  unsigned long long npts[2];  // [set]: front points found
+  unsigned long long pad[14];
+  unsigned long long amax[2][NSUB][16];  // [set][sub][0]: max|u|, [1]: max|v| (bit patterns)
 };
 struct LsArgs {
   int mx, my;          // corners per row / column (nx + 1, ny + 1)
@@ -139,7 +142,9 @@ struct LsArgs {
   double* W;           // stage output (distance: the field, in place; velocity: the output)
   const double* vel;   // corner velocity [2][my][mx]
   LsCtl* lc;
+  int set;             // the call's set of lc
 };
+hipError_t launch_ls_init(LsCtl* lc, hipStream_t s);  // both sets of lc cleared
 hipError_t launch_ls_alpha(const LsArgs& a, hipStream_t s);
 hipError_t launch_ls_images(const LsArgs& a, double* S, hipStream_t s);
 hipError_t launch_ls_stage(const LsArgs& a, hipStream_t s);

@@ -21,9 +21,10 @@
 // tanh, whose last bits depend on the math library.
 //
 // Kernels:
-//  ls_clear / ls_alpha   max|u|, max|v| of the corner velocity into 64
+//  ls_alpha              max|u|, max|v| of the corner velocity into 64
 //                        sub-slots (bit patterns of non-negative doubles order
-//                        like the values, so atomicMax on them is exact);
+//                        like the values, so atomicMax on them is exact) of the
+//                        step's set, clearing the other set for the next step;
 //  ls_stage              one RK stage: 32 x 16 corner tile with a 3-corner
 //                        halo in LDS (read without the ghost rule where the
 //                        halo lies inside the grid), the one-sided differences
@@ -75,9 +76,9 @@ __device__ __forceinline__ int ls_map(int gi, int n, int blo, int bhi, int& edge
   return gi;
 }
 
-__device__ __forceinline__ void read_amax(const LsCtl* lc, double* sh, double& mu, double& mv) {
+__device__ __forceinline__ void read_amax(const LsCtl* lc, int set, double* sh, double& mu, double& mv) {
   if (threadIdx.x < NSUB) {
-    double a = as_double(lc->amax[threadIdx.x][0]), b = as_double(lc->amax[threadIdx.x][1]);
+    double a = as_double(lc->amax[set][threadIdx.x][0]), b = as_double(lc->amax[set][threadIdx.x][1]);
 #pragma unroll
     for (int off = NSUB / 2; off > 0; off >>= 1) {
       a = __builtin_fmax(a, __shfl_xor(a, off));
@@ -104,16 +105,25 @@ __device__ __forceinline__ double ls_weno5(double v0, double v1, double v2, doub
 
 }  // namespace
 
-__global__ void ls_clear_kernel(LsCtl* lc) {
+__global__ void ls_init_kernel(LsCtl* lc) {
   const int t = threadIdx.x;
   if (t < NSUB) {
-    lc->amax[t][0] = 0ull;
-    lc->amax[t][1] = 0ull;
+    for (int set = 0; set < 2; ++set) {
+      lc->amax[set][t][0] = 0ull;
+      lc->amax[set][t][1] = 0ull;
+    }
   }
-  if (t == 0) lc->npts = 0ull;
+  if (t < 2) lc->npts[t] = 0ull;
 }
 
-__global__ __launch_bounds__(LS_THREADS) void ls_alpha_kernel(const double* vel, long long nc, LsCtl* lc) {
+// max |u|, max |v| into the sub-slots of set `set`; the first workgroup clears
+// the other set's sub-slots for the next step.
+__global__ __launch_bounds__(LS_THREADS) void ls_alpha_kernel(const double* vel, long long nc, LsCtl* lc,
+                                                              int set) {
+  if (blockIdx.x == 0 && threadIdx.x < NSUB) {
+    lc->amax[1 - set][threadIdx.x][0] = 0ull;
+    lc->amax[1 - set][threadIdx.x][1] = 0ull;
+  }
   __shared__ double red[2][LS_THREADS / 64];
   double mu = 0.0, mv = 0.0;
   for (long long k = (long long)blockIdx.x * LS_THREADS + threadIdx.x; k < nc;
@@ -137,8 +147,8 @@ __global__ __launch_bounds__(LS_THREADS) void ls_alpha_kernel(const double* vel,
       mu = __builtin_fmax(mu, red[0][k]);
       mv = __builtin_fmax(mv, red[1][k]);
     }
-    atomicMax(&lc->amax[blockIdx.x % NSUB][0], as_bits(mu));
-    atomicMax(&lc->amax[blockIdx.x % NSUB][1], as_bits(mv));
+    atomicMax(&lc->amax[set][blockIdx.x % NSUB][0], as_bits(mu));
+    atomicMax(&lc->amax[set][blockIdx.x % NSUB][1], as_bits(mv));
   }
 }
 
@@ -199,7 +209,7 @@ __global__ __launch_bounds__(LST_THREADS) void ls_stage_kernel(LsArgs a) {
     QY[e][c] = (T[e + 1][c + 3] - T[e][c + 3]) * a.idy;
   }
   double mu, mv;
-  read_amax(a.lc, sh, mu, mv);  // contains a barrier
+  read_amax(a.lc, a.set, sh, mu, mv);  // contains a barrier
   const double ax = mu + a.s_f, ay = mv + a.s_f;
 
   const int tx = tid % LTX, ty = tid / LTX;
@@ -293,7 +303,8 @@ __global__ __launch_bounds__(LS_THREADS) void ls_front_kernel(LsArgs a, double* 
   }
   const int total = __shfl(incl, 63);
   unsigned long long base = 0;
-  if (lane == 63 && total > 0) base = atomicAdd(&a.lc->npts, (unsigned long long)total);
+  if (lane == 63 && total > 0) base = atomicAdd(&a.lc->npts[a.set], (unsigned long long)total);
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.lc->npts[1 - a.set] = 0ull;  // for the next call
   base = __shfl(base, 63);
   const unsigned long long at = base + (unsigned long long)(incl - cnt);
   for (int c = 0; c < cnt; ++c) {
@@ -317,7 +328,7 @@ __global__ __launch_bounds__(LS_THREADS) void ls_distance_kernel(LsArgs a, const
   const int ntx = (a.mx + DTX - 1) / DTX;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int i0 = (tile % ntx) * DTX, j0 = (tile / ntx) * DTY;
-  const long long np = (long long)a.lc->npts;
+  const long long np = (long long)a.lc->npts[a.set];
   if (np == 0) return;  // no front: the field stays as it is
   const int i1 = min(i0 + DTX, a.mx) - 1, j1 = min(j0 + DTY, a.my) - 1;
   // tile box and centre
@@ -437,12 +448,16 @@ __global__ __launch_bounds__(LS_THREADS) void ls_velocity_kernel(LsArgs a, const
   vel[nc + k] = 0.25 * ((vv[0] + vv[1]) + (vv[2] + vv[3]));
 }
 
+hipError_t launch_ls_init(LsCtl* lc, hipStream_t s) {
+  hipLaunchKernelGGL(ls_init_kernel, dim3(1), dim3(64), 0, s, lc);
+  return hipGetLastError();
+}
+
 hipError_t launch_ls_alpha(const LsArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(ls_clear_kernel, dim3(1), dim3(64), 0, s, a.lc);
   const long long nc = (long long)a.mx * a.my;
   long long nb = (nc + LS_THREADS - 1) / LS_THREADS;
   if (nb > 1024) nb = 1024;
-  hipLaunchKernelGGL(ls_alpha_kernel, dim3((unsigned)nb), dim3(LS_THREADS), 0, s, a.vel, nc, a.lc);
+  hipLaunchKernelGGL(ls_alpha_kernel, dim3((unsigned)nb), dim3(LS_THREADS), 0, s, a.vel, nc, a.lc, a.set);
   return hipGetLastError();
 }
 
@@ -460,7 +475,6 @@ hipError_t launch_ls_stage(const LsArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_ls_front(const LsArgs& a, double* pts, hipStream_t s) {
-  hipLaunchKernelGGL(ls_clear_kernel, dim3(1), dim3(64), 0, s, a.lc);
   const long long nc = (long long)a.mx * a.my;
   const unsigned nb = (unsigned)((nc + LS_THREADS - 1) / LS_THREADS);
   hipLaunchKernelGGL(ls_front_kernel, dim3(nb), dim3(LS_THREADS), 0, s, a, pts);

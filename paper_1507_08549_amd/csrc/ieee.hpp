@@ -39,16 +39,20 @@ __device__ __forceinline__ double cr_div(double a, double b) {
 }
 
 // cr_div for a positive normal denominator whose reciprocal is normal and a
-// quotient that is zero or normal: the faithful quotient from the hardware
-// reciprocal refined by two Newton steps and one correction step (q0 = a r,
+// quotient that is zero or normal: a faithful quotient from the hardware
+// reciprocal, one Newton step and one correction step (q0 = a r,
 // q = q0 + (a - q0 b) r), without the scaling and special-value steps of the
 // general division sequence, then the same neighbour check (with b > 0 the
-// true quotient lies on the side of sign(t) alone).  The WENO face values are such quotients: their
-// denominators, products of sums of weights, lie between about 3e-47
+// true quotient lies on the side of sign(t) alone).  With r = (1 + d) / b
+// after the Newton step, q0 = Q (1 + D) with D = d + (rounding of a r), and
+// the correction leaves Q (1 - D (d + e)) before its rounding (e: rounding of
+// the residual), so the relative error before the last rounding is about
+// d^2: the hardware reciprocal's error (measured at most 2^-24.4) is squared
+// twice, far below half an ulp.  The WENO face values are such quotients:
+// their denominators, products of sums of weights, lie between about 3e-47
 // (eps = 1e-6) and the overflow of the numerator that comes with them.
 __device__ __forceinline__ double cr_div_pos_normal(double a, double b) {
   double r = __builtin_amdgcn_rcp(b);
-  r = __builtin_fma(r, __builtin_fma(-b, r, 1.0), r);
   r = __builtin_fma(r, __builtin_fma(-b, r, 1.0), r);
   const double q0 = a * r;
   const double q = __builtin_fma(__builtin_fma(-q0, b, a), r, q0);

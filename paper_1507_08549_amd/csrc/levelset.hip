@@ -35,16 +35,17 @@
 //                        wavefront to reserve space (the order of the points is
 //                        not fixed; nothing downstream depends on it);
 //  ls_distance           nearest-point search and blend: 32 x 16 corners per
-//                        workgroup, two per work item; points streamed through
-//                        LDS.  The minimum is taken over squared distances and
-//                        rooted once (the square root is monotone and correctly
+//                        workgroup, a 16 x 8 quarter per wavefront, two corners
+//                        per work item; points streamed through LDS.  The
+//                        minimum is taken over squared distances and rooted
+//                        once (the square root is monotone and correctly
 //                        rounded, so this equals the minimum of the roots).
-//                        A workgroup first bounds the distance of all its
-//                        corners (nearest point to the tile centre plus the
-//                        half diagonal) and skips every point whose distance to
-//                        the tile's box exceeds that bound with a relative
-//                        margin of 1e-9, far above rounding, so the skipped
-//                        points can never hold the minimum.
+//                        Every corner starts from the point nearest to the tile
+//                        centre; a point whose distance to the tile's box, then
+//                        to the quarter's box, exceeds the largest current
+//                        minimum of that box's corners (with a relative margin
+//                        of 1e-9, far above rounding) is skipped: it cannot hold
+//                        the minimum of any of them.
 #include "stage_kernel.hpp"
 
 namespace hy {
@@ -313,95 +314,170 @@ __global__ __launch_bounds__(LS_THREADS) void ls_front_kernel(LsArgs a, double* 
   }
 }
 
-// Distance and blend.  Corner tile 32 x 16 (two corners per work item, rows
-// ty and ty + 8); points staged through LDS in chunks.
-constexpr int DTX = 32, DTY = 16, DCH = 512;
-constexpr int DRS = LS_THREADS / DTX;  // row stride of a work item's corners
-constexpr int DR = DTY / DRS;          // corners per work item
-static_assert(DR * DRS == DTY && LS_THREADS % DTX == 0, "distance tile shape");
+// Distance and blend.  Corner tile 32 x 16 per workgroup; each wavefront owns a
+// 16 x 8 quarter of it, two corners per work item (rows q and q + 4 of the
+// quarter, one column).  Points are streamed in chunks: the workgroup keeps
+// those a corner of its tile may be nearest to, each wavefront keeps, of
+// those, the ones a corner of its quarter may be nearest to, and loops over
+// its own list.
+constexpr int DTX = 32, DTY = 16, DQX = 16, DQY = 8;
+constexpr int DW = LS_THREADS / 64;  // wavefronts per workgroup
+constexpr int DCH = 248;             // points per chunk (20 KB of LDS: 8 workgroups per CU)
+static_assert((DTX / DQX) * (DTY / DQY) == DW && DQX * DQY == 2 * 64 && DCH <= LS_THREADS,
+              "distance tile shape");
+
+// Max of a non-negative x over the wavefront, in every lane.
+__device__ __forceinline__ double wave_max_all(double x) {
+  const long long m = __double_as_longlong(wave_max_nonneg(x));
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)m, 63);
+  const unsigned hi = __builtin_amdgcn_readlane((unsigned)((unsigned long long)m >> 32), 63);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Squared distance from (qx, qy) to the box [x0, x1] x [y0, y1].
+__device__ __forceinline__ double box_dist2(double qx, double qy, double x0, double x1, double y0, double y1) {
+  const double ddx = qx < x0 ? x0 - qx : (qx > x1 ? qx - x1 : 0.0);
+  const double ddy = qy < y0 ? y0 - qy : (qy > y1 ? qy - y1 : 0.0);
+  return ddx * ddx + ddy * ddy;
+}
 
 __global__ __launch_bounds__(LS_THREADS) void ls_distance_kernel(LsArgs a, const double* pts, double* dist) {
-  __shared__ double P[2][DCH];
-  __shared__ int nkeep;
-  __shared__ double red[LS_THREADS / 64];
-  const int tid = threadIdx.x;
+  __shared__ double P[2][DCH];      // the tile's candidates of a chunk
+  __shared__ double Q[DW][2][DCH];  // each wavefront's own candidates
+  __shared__ double red[3][DW];     // pass 1: each wavefront's nearest point
+  __shared__ double ub[DW];         // each quarter's bound
+  __shared__ int nkeep[2];          // candidates of the chunk (alternating)
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform in the wavefront
   const int ntx = (a.mx + DTX - 1) / DTX;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int i0 = (tile % ntx) * DTX, j0 = (tile / ntx) * DTY;
   const long long np = (long long)a.lc->npts[a.set];
   if (np == 0) return;  // no front: the field stays as it is
+  const double2* pp = reinterpret_cast<const double2*>(pts);  // (x, y) of each point
   const int i1 = min(i0 + DTX, a.mx) - 1, j1 = min(j0 + DTY, a.my) - 1;
-  // tile box and centre
-  const double bx0 = a.xlo + (double)i0 * a.dx, bx1 = a.xlo + (double)i1 * a.dx;
-  const double by0 = a.ylo + (double)j0 * a.dy, by1 = a.ylo + (double)j1 * a.dy;
-  const double cx = 0.5 * (bx0 + bx1), cy = 0.5 * (by0 + by1);
-  const double hx = 0.5 * (bx1 - bx0), hy = 0.5 * (by1 - by0);
-  const double half_diag = __builtin_sqrt(hx * hx + hy * hy);
+  const double tx0 = a.xlo + (double)i0 * a.dx, tx1 = a.xlo + (double)i1 * a.dx;
+  const double ty0 = a.ylo + (double)j0 * a.dy, ty1 = a.ylo + (double)j1 * a.dy;
 
-  // pass 1: nearest point to the tile centre
-  double best_c = __builtin_inf();
-  for (long long k = tid; k < np; k += LS_THREADS) {
-    const double ex = cx - pts[2 * k], ey = cy - pts[2 * k + 1];
-    best_c = __builtin_fmin(best_c, ex * ex + ey * ey);
-  }
+  // pass 1: the point nearest to the tile centre
+  {
+    const double cx = 0.5 * (tx0 + tx1), cy = 0.5 * (ty0 + ty1);
+    double bc = __builtin_inf(), bx = 0.0, by = 0.0;
+    for (long long k = tid; k < np; k += 2 * LS_THREADS) {
+      const double2 p0 = pp[k];
+      const double2 p1 = k + LS_THREADS < np ? pp[k + LS_THREADS] : p0;
+      const double ex = cx - p0.x, ey = cy - p0.y, fx = cx - p1.x, fy = cy - p1.y;
+      const double d = ex * ex + ey * ey, e = fx * fx + fy * fy;
+      if (d < bc) { bc = d; bx = p0.x; by = p0.y; }
+      if (e < bc) { bc = e; bx = p1.x; by = p1.y; }
+    }
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) best_c = __builtin_fmin(best_c, __shfl_xor(best_c, off));
-  if ((tid & 63) == 0) red[tid / 64] = best_c;
+    for (int off = 32; off > 0; off >>= 1) {
+      const double od = __shfl_xor(bc, off), ox = __shfl_xor(bx, off), oy = __shfl_xor(by, off);
+      if (od < bc) { bc = od; bx = ox; by = oy; }
+    }
+    if (lane == 0) { red[0][w] = bc; red[1][w] = bx; red[2][w] = by; }
+  }
   __syncthreads();
-  best_c = red[0];
-  for (int k = 1; k < LS_THREADS / 64; ++k) best_c = __builtin_fmin(best_c, red[k]);
-  // every corner of the tile is within (|centre - p*| + half diagonal) of a point
-  const double ub = __builtin_sqrt(best_c) + half_diag;
-  const double ub2 = (ub * ub) * (1.0 + 1e-9);
+  double px = red[1][0], py = red[2][0];
+  {
+    double b = red[0][0];
+    for (int k = 1; k < DW; ++k)
+      if (red[0][k] < b) { b = red[0][k]; px = red[1][k]; py = red[2][k]; }
+  }
 
-  const int tx = tid % DTX, ty = tid / DTX;
-  const int i = i0 + tx;
+  // this work item's corners and its wavefront's quarter
+  const int qi0 = i0 + (w % (DTX / DQX)) * DQX, qj0 = j0 + (w / (DTX / DQX)) * DQY;
+  const int i = qi0 + (lane % DQX);
   const double x = a.xlo + (double)i * a.dx;
-  double yv[DR], best[DR];
+  const bool wave_on = qi0 < a.mx && qj0 < a.my;  // the quarter holds a corner of the grid
+  const int qi1 = min(qi0 + DQX, a.mx) - 1, qj1 = min(qj0 + DQY, a.my) - 1;
+  const double qx0 = a.xlo + (double)qi0 * a.dx, qx1 = a.xlo + (double)qi1 * a.dx;
+  const double qy0 = a.ylo + (double)qj0 * a.dy, qy1 = a.ylo + (double)qj1 * a.dy;
+  double yv[2], best[2];
+  bool on[2];
 #pragma unroll
-  for (int r = 0; r < DR; ++r) {
-    yv[r] = a.ylo + (double)(j0 + ty + DRS * r) * a.dy;
-    best[r] = __builtin_inf();
+  for (int r = 0; r < 2; ++r) {
+    const int j = qj0 + (lane / DQX) + 4 * r;
+    yv[r] = a.ylo + (double)j * a.dy;
+    on[r] = i < a.mx && j < a.my;
+    // the point nearest to the tile centre is a candidate of every corner
+    const double ex = x - px, ey = yv[r] - py;
+    best[r] = ex * ex + ey * ey;
   }
-  for (long long c0 = 0; c0 < np; c0 += DCH) {
+  // Bounds: every corner's minimum is at most its current best, so a point
+  // whose distance to a box exceeds the largest current best of the box's
+  // corners (with a relative margin of 1e-9, far above rounding) is nearest to
+  // none of them.
+  const double qb = wave_max_all(__builtin_fmax(on[0] ? best[0] : 0.0, on[1] ? best[1] : 0.0));
+  if (lane == 0) ub[w] = qb;
+  if (tid == 0) nkeep[0] = 0;
+  __syncthreads();
+  double tb = ub[0];
+  for (int k = 1; k < DW; ++k) tb = __builtin_fmax(tb, ub[k]);
+  tb *= 1.0 + 1e-9;
+  const double wb = qb * (1.0 + 1e-9);
+
+  double2 q = {0.0, 0.0};  // this work item's point of the chunk
+  if (tid < min(np, (long long)DCH)) q = pp[tid];
+  int c = 0;
+  for (long long c0 = 0; c0 < np; c0 += DCH, c ^= 1) {
     const int m = (int)min((long long)DCH, np - c0);
-    __syncthreads();  // previous chunk consumed
-    if (tid == 0) nkeep = 0;
-    __syncthreads();
-    for (int k = tid; k < m; k += LS_THREADS) {
-      const double qx = pts[2 * (c0 + k)], qy = pts[2 * (c0 + k) + 1];
-      // squared distance from the point to the tile's box
-      const double ddx = qx < bx0 ? bx0 - qx : (qx > bx1 ? qx - bx1 : 0.0);
-      const double ddy = qy < by0 ? by0 - qy : (qy > by1 ? qy - by1 : 0.0);
-      if (ddx * ddx + ddy * ddy <= ub2) {
-        const int at = atomicAdd(&nkeep, 1);
-        P[0][at] = qx;
-        P[1][at] = qy;
-      }
+    if (tid < m && box_dist2(q.x, q.y, tx0, tx1, ty0, ty1) <= tb) {
+      const int at = atomicAdd(&nkeep[c], 1);
+      P[0][at] = q.x;
+      P[1][at] = q.y;
     }
-    __syncthreads();
-    const int nk = nkeep;
-    for (int k = 0; k < nk; ++k) {
-      const double ex = x - P[0][k];
+    if (tid < DCH && c0 + DCH + tid < np) q = pp[c0 + DCH + tid];  // next chunk, loaded during this one
+    __syncthreads();  // the chunk's candidates are complete
+    const int nk = nkeep[c];
+    if (tid == 0) nkeep[c ^ 1] = 0;  // last read in the previous chunk
+    if (wave_on) {
+      int nq = 0;
+      for (int k0 = 0; k0 < nk; k0 += 64) {
+        const int k = k0 + lane;
+        double sx = 0.0, sy = 0.0;
+        bool keep = false;
+        if (k < nk) {
+          sx = P[0][k];
+          sy = P[1][k];
+          keep = box_dist2(sx, sy, qx0, qx1, qy0, qy1) <= wb;
+        }
+        const unsigned long long bal = __ballot(keep);
+        if (keep) {
+          const int at = nq + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
+          Q[w][0][at] = sx;
+          Q[w][1][at] = sy;
+        }
+        nq += __popcll(bal);
+      }
+      __syncwarp();
+#pragma unroll 4
+      for (int k = 0; k < nq; ++k) {
+        const double ex = x - Q[w][0][k];
 #pragma unroll
-      for (int r = 0; r < DR; ++r) {
-        const double ey = yv[r] - P[1][k];
-        best[r] = __builtin_fmin(best[r], ex * ex + ey * ey);
+        for (int r = 0; r < 2; ++r) {
+          const double ey = yv[r] - Q[w][1][k];
+          best[r] = __builtin_fmin(best[r], ex * ex + ey * ey);
+        }
       }
     }
+    __syncthreads();  // the chunk's candidates are consumed
   }
-  if (i >= a.mx) return;
   const double D = a.dx < a.dy ? a.dx : a.dy;
-  const double w = D / 3.0, d0 = 3.0 * D;
-  const double den = 1.0 - tanh(-d0 / w);
+  const double wd = D / 3.0, d0 = 3.0 * D;
 #pragma unroll
-  for (int r = 0; r < DR; ++r) {
-    const int j = j0 + ty + DRS * r;
-    if (j >= a.my) continue;
+  for (int r = 0; r < 2; ++r) {
+    if (!on[r]) continue;
+    const int j = qj0 + (lane / DQX) + 4 * r;
     const size_t kc = (size_t)j * a.mx + i;
     const double d = cr_sqrt(best[r]);
     const double s = a.W[kc];
-    const double h = (1.0 - tanh((d - d0) / w)) / den;
+    const double t = (d - d0) / wd;
+    // tanh(t) rounds to 1 from t = 22 on (1 - tanh(22) is about 1.6e-19), where
+    // the blend weight is 0
+    const double h = t < 22.0 ? (1.0 - tanh(t)) / (1.0 - tanh(-d0 / wd)) : 0.0;
     const double sd = s < 0.0 ? -d : d;
     a.W[kc] = h * s + (1.0 - h) * sd;
     if (dist) dist[kc] = d;

@@ -31,9 +31,10 @@
 //                        (times 1/spacing) once per edge in LDS, four
 //                        reconstructions per corner;
 //  ls_front              front points, one work item per corner (its zero test,
-//                        its right edge, its upper edge), one atomic per
-//                        wavefront to reserve space (the order of the points is
-//                        not fixed; nothing downstream depends on it);
+//                        its right edge, its upper edge), 16 x 16 corners per
+//                        workgroup, one atomic per workgroup with points to
+//                        reserve space (the order of the points is not fixed;
+//                        nothing downstream depends on it);
 //  ls_distance           nearest-point search and blend: 32 x 16 corners per
 //                        workgroup, a 16 x 8 quarter per wavefront, two corners
 //                        per work item; points streamed through LDS.  The
@@ -262,13 +263,21 @@ __global__ __launch_bounds__(LS_THREADS) void ls_images_kernel(LsArgs a, double*
   if (si != i || sj != j) S[(size_t)j * a.mx + i] = S[(size_t)sj * a.mx + si];
 }
 
+// Front points of a 16 x 16 corner tile per workgroup: a prefix sum of the
+// counts over the workgroup and one atomic per workgroup that has points.
+constexpr int FTX = 16, FTY = 16;
+static_assert(FTX * FTY == LS_THREADS, "front tile shape");
+
 __global__ __launch_bounds__(LS_THREADS) void ls_front_kernel(LsArgs a, double* pts) {
-  const long long nc = (long long)a.mx * a.my;
-  const long long k = (long long)blockIdx.x * LS_THREADS + threadIdx.x;
+  __shared__ int wsum[LS_THREADS / 64];
+  __shared__ unsigned long long base;
+  const int ntx = (a.mx + FTX - 1) / FTX;
+  const int i = (blockIdx.x % ntx) * FTX + (threadIdx.x % FTX);
+  const int j = (blockIdx.x / ntx) * FTY + (threadIdx.x / FTX);
   double px[3], py[3];
   int cnt = 0;
-  if (k < nc) {
-    const int j = (int)(k / a.mx), i = (int)(k % a.mx);
+  if (i < a.mx && j < a.my) {
+    const size_t k = (size_t)j * a.mx + i;
     const double* S = a.V;
     const double s = S[k];
     const double x = a.xlo + (double)i * a.dx, y = a.ylo + (double)j * a.dy;
@@ -294,20 +303,27 @@ __global__ __launch_bounds__(LS_THREADS) void ls_front_kernel(LsArgs a, double* 
       }
     }
   }
-  // wavefront prefix sum of the counts, one atomic per wavefront
-  const int lane = threadIdx.x & 63;
-  int incl = cnt;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int incl = cnt;  // inclusive prefix sum over the wavefront
 #pragma unroll
   for (int off = 1; off < 64; off <<= 1) {
     const int o = __shfl_up(incl, off);
     if (lane >= off) incl += o;
   }
-  const int total = __shfl(incl, 63);
-  unsigned long long base = 0;
-  if (lane == 63 && total > 0) base = atomicAdd(&a.lc->npts[a.set], (unsigned long long)total);
-  if (blockIdx.x == 0 && threadIdx.x == 0) a.lc->npts[1 - a.set] = 0ull;  // for the next call
-  base = __shfl(base, 63);
-  const unsigned long long at = base + (unsigned long long)(incl - cnt);
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  int before = 0, total = 0;
+#pragma unroll
+  for (int q = 0; q < LS_THREADS / 64; ++q) {
+    before += q < w ? wsum[q] : 0;
+    total += wsum[q];
+  }
+  if (threadIdx.x == 0) {
+    base = total > 0 ? atomicAdd(&a.lc->npts[a.set], (unsigned long long)total) : 0ull;
+    if (blockIdx.x == 0) a.lc->npts[1 - a.set] = 0ull;  // for the next call
+  }
+  __syncthreads();
+  const unsigned long long at = base + (unsigned long long)(before + incl - cnt);
   for (int c = 0; c < cnt; ++c) {
     pts[2 * (at + c)] = px[c];
     pts[2 * (at + c) + 1] = py[c];
@@ -335,9 +351,10 @@ __device__ __forceinline__ double wave_max_all(double x) {
 }
 
 // Squared distance from (qx, qy) to the box [x0, x1] x [y0, y1].
+// (With x0 <= x1 at most one of x0 - qx, qx - x1 is positive.)
 __device__ __forceinline__ double box_dist2(double qx, double qy, double x0, double x1, double y0, double y1) {
-  const double ddx = qx < x0 ? x0 - qx : (qx > x1 ? qx - x1 : 0.0);
-  const double ddy = qy < y0 ? y0 - qy : (qy > y1 ? qy - y1 : 0.0);
+  const double ddx = __builtin_fmax(__builtin_fmax(x0 - qx, qx - x1), 0.0);
+  const double ddy = __builtin_fmax(__builtin_fmax(y0 - qy, qy - y1), 0.0);
   return ddx * ddx + ddy * ddy;
 }
 
@@ -551,8 +568,7 @@ hipError_t launch_ls_stage(const LsArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_ls_front(const LsArgs& a, double* pts, hipStream_t s) {
-  const long long nc = (long long)a.mx * a.my;
-  const unsigned nb = (unsigned)((nc + LS_THREADS - 1) / LS_THREADS);
+  const unsigned nb = (unsigned)(((a.mx + FTX - 1) / FTX) * ((a.my + FTY - 1) / FTY));
   hipLaunchKernelGGL(ls_front_kernel, dim3(nb), dim3(LS_THREADS), 0, s, a, pts);
   return hipGetLastError();
 }

@@ -128,8 +128,22 @@ __global__ __launch_bounds__(LS_THREADS) void ls_alpha_kernel(const double* vel,
   }
   __shared__ double red[2][LS_THREADS / 64];
   double mu = 0.0, mv = 0.0;
-  for (long long k = (long long)blockIdx.x * LS_THREADS + threadIdx.x; k < nc;
-       k += (long long)gridDim.x * LS_THREADS) {
+  const long long stride = (long long)gridDim.x * LS_THREADS;
+  long long k = (long long)blockIdx.x * LS_THREADS + threadIdx.x;
+  for (; k + 3 * stride < nc; k += 4 * stride) {  // eight loads in flight
+    double u[4], v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      u[q] = vel[k + q * stride];
+      v[q] = vel[nc + k + q * stride];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      mu = __builtin_fmax(mu, __builtin_fabs(u[q]));
+      mv = __builtin_fmax(mv, __builtin_fabs(v[q]));
+    }
+  }
+  for (; k < nc; k += stride) {
     mu = __builtin_fmax(mu, __builtin_fabs(vel[k]));
     mv = __builtin_fmax(mv, __builtin_fabs(vel[nc + k]));
   }

@@ -352,7 +352,7 @@ __global__ __launch_bounds__(LS_THREADS) void ls_front_kernel(LsArgs a, double* 
 // its own list.
 constexpr int DTX = 32, DTY = 16, DQX = 16, DQY = 8;
 constexpr int DW = LS_THREADS / 64;  // wavefronts per workgroup
-constexpr int DCH = 248;             // points per chunk (20 KB of LDS: 8 workgroups per CU)
+constexpr int DCH = 248;             // points per chunk (20 KB of LDS per workgroup)
 static_assert((DTX / DQX) * (DTY / DQY) == DW && DQX * DQY == 2 * 64 && DCH <= LS_THREADS,
               "distance tile shape");
 

@@ -330,24 +330,31 @@ __global__ __launch_bounds__(64 * NL) void vjp_line_kernel(VjpPass P) {
   } else {
     // lanes run down columns: stage the workgroup's points with row-major
     // loads (consecutive work items take consecutive columns), the own
-    // points' state and adjoint with them
-    for (int t = tid; t < NL * LP; t += NT) {
-      const int b = t % NL, p = t / NL;
-      R u4[4];
-      load_state(a0 - 6 + p, b0 + b, u4);
-      stage_point(p, b, u4);
-      if (p >= 3 && p < 67) {
+    // points' state and adjoint with them.  A work item stages at most two
+    // points and one adjoint; all its loads are issued before any of them is
+    // used.
+    static_assert(NL * LP <= 2 * NT && NL * 64 == NT, "y staging shape");
+    const int t2 = tid + NT;
+    const bool two = t2 < NL * LP;
+    const int b1 = tid % NL, p1 = tid / NL, b2 = t2 % NL, p2 = t2 / NL;
+    R u1[4], u2[4], m4[4];
+    load_state(a0 - 6 + p1, b0 + b1, u1);
+    if (two) load_state(a0 - 6 + p2, b0 + b2, u2);
+    load_mu(a0 - 3 + p1, b0 + b1, m4);  // (b1, p1) = (line, lane) of the adjoint
+    stage_point(p1, b1, u1);
+    if (p1 >= 3 && p1 < 67) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) sU[c][b][p - 3] = u4[c];
+      for (int c = 0; c < 4; ++c) sU[c][b1][p1 - 3] = u1[c];
+    }
+    if (two) {
+      stage_point(p2, b2, u2);
+      if (p2 >= 3 && p2 < 67) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sU[c][b2][p2 - 3] = u2[c];
       }
     }
-    for (int t = tid; t < NL * 64; t += NT) {
-      const int b = t % NL, l = t / NL;
-      R m4[4];
-      load_mu(a0 - 3 + l, b0 + b, m4);
 #pragma unroll
-      for (int c = 0; c < 4; ++c) sM[c][b][l] = m4[c];
-    }
+    for (int c = 0; c < 4; ++c) sM[c][b1][p1] = m4[c];
   }
   __syncthreads();
   if constexpr (STAGE_OWN) {

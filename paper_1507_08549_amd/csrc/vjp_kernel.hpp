@@ -317,16 +317,15 @@ __global__ __launch_bounds__(64 * NL) void vjp_line_kernel(VjpPass P) {
   };
   if constexpr (!STAGE_OWN) {
     // lanes run along rows: each wavefront stages its own line, lane l its own
-    // point (p = l + 3) and lanes 0..4 the five others (p = 0, 1, 2, 67, 68)
+    // point (p = l + 3) and lanes 0..4 the five others (p = 0, 1, 2, 67, 68);
+    // every load is issued before any of them is used
+    const int ph = L < 3 ? L : 64 + L;
+    R uh[4];
+    if (L < 5) load_state(a0 - 6 + ph, line, uh);
     load_state(k, line, cu);
     load_mu(k, line, mu);
     stage_point(L + 3, wv, cu);
-    if (L < 5) {
-      const int p = L < 3 ? L : 64 + L;
-      R u4[4];
-      load_state(a0 - 6 + p, line, u4);
-      stage_point(p, wv, u4);
-    }
+    if (L < 5) stage_point(ph, wv, uh);
   } else {
     // lanes run down columns: stage the workgroup's points with row-major
     // loads (consecutive work items take consecutive columns), the own

@@ -4,7 +4,8 @@ through the C ABI.
 Bit for bit: the advected corner field after several SSP-RK3 steps (every
 boundary combination, grids smaller than one tile and ragged ones, with and
 without a flame speed, periodic inputs whose image corners disagree), the
-corner velocity, the set of front points and the nearest distances.  The
+corner velocity, the set of front points and the nearest distances (also
+with over a thousand points in several chunks, and with a single one).  The
 re-distanced field goes through tanh, whose last bits belong to the math
 library: it is compared within 4e-15 (|S| + d), a few units in the last place
 of the blend's two terms.  Full size: the flame-front workload on 1025^2
@@ -126,6 +127,54 @@ def test_ls_front_and_distance_bitwise(torch, hydro, oracle_mod, shape):
     tol = 4e-15 * (np.abs(S) + want_d)
     err = np.abs(got_S - want_S)
     assert np.all(err <= tol), (err / np.maximum(tol, 1e-300)).max()
+
+
+def _many_contours(prm, seed):
+    """A field with many zero lines (over a thousand front points on grids of
+    about 150^2 corners), so the search streams several chunks of points."""
+    x, y = inputs.corners(prm)
+    X, Y = np.meshgrid(x, y)
+    rng = np.random.default_rng(seed)
+    a, b = rng.uniform(0, 2 * np.pi, 2)
+    return np.ascontiguousarray(np.sin(23.0 * X + a) * np.cos(17.0 * Y + b) + 0.05 * np.sin(3.0 * X * Y + 1.0))
+
+
+def _check_redistance(torch, hydro, oracle_mod, prm, S):
+    ls = oracle_mod.LevelSet(prm)
+    s = hydro.Solver(prm)
+    try:
+        Sd = _dev(torch, S)
+        dist = torch.zeros_like(Sd)
+        n = s.ls_redistance(Sd, dist)
+        got_S, got_d = Sd.cpu().numpy(), dist.cpu().numpy()
+    finally:
+        s.close()
+    want_S, want_d, wn = ls.redistance(S)
+    assert n == wn
+    _same(got_d, want_d, "distance")
+    tol = 4e-15 * (np.abs(S) + want_d)
+    err = np.abs(got_S - want_S)
+    assert np.all(err <= tol), (err / np.maximum(tol, 1e-300)).max()
+    return n
+
+
+@pytest.mark.parametrize("shape,seed", [((160, 120), 1), ((97, 203), 2)])
+def test_ls_distance_many_points_bitwise(torch, hydro, oracle_mod, shape, seed):
+    """Every corner's distance bit for bit with front points spread over the
+    whole grid in several chunks, on ragged tiles."""
+    nx, ny = shape
+    prm = inputs.make_params(nx, ny, 0.0, 1.0, 0.0, 1.0, [T, T, T, T], 1.4)
+    n = _check_redistance(torch, hydro, oracle_mod, prm, _many_contours(prm, seed))
+    assert n > 1000
+
+
+def test_ls_distance_single_point(torch, hydro, oracle_mod):
+    """One front point (a corner with S = 0, no sign change): every distance is
+    the distance to that corner, bit for bit."""
+    prm = inputs.make_params(70, 45, 0.0, 1.0, 0.0, 0.6, [T, T, T, T], 1.4)
+    S = 1.0 + np.random.default_rng(4).uniform(0, 1, (46, 71))
+    S[40, 3] = 0.0
+    assert _check_redistance(torch, hydro, oracle_mod, prm, S) == 1
 
 
 def test_ls_redistance_without_front(torch, hydro):

@@ -74,7 +74,9 @@ enum { HYDRO_COMPONENTWISE = 0, HYDRO_CHARACTERISTIC = 1 };
  *  cfl         Courant number c_cfl of the CFL step (Sect. 5.3).
  *  weno_eps    epsilon of the WENO weights (1e-6 is the usual choice; at least
  *              1e-30, so that the two reconstructions of a face can share one
- *              denominator without underflow).
+ *              denominator without underflow; at least 1e-12 with
+ *              HYDRO_FP32_BULK, whose single-precision weights reach
+ *              1 / eps^2 on flat data).  HYDRO_E_INVALID otherwise.
  *  precision   HYDRO_FP64: every operation in FP64.  HYDRO_FP32_BULK: primitive
  *              variables, split fluxes, reconstructions and the divergence in
  *              FP32; stage accumulation, the CFL / LF-speed reductions and the

@@ -78,6 +78,9 @@ int check_params(const hydro_params* p) {
   if (p->geometry != HYDRO_CARTESIAN && p->geometry != HYDRO_CYLINDRICAL) return HYDRO_E_INVALID;
   if (p->geometry == HYDRO_CYLINDRICAL && p->xlo < 0.0) return HYDRO_E_INVALID;
   if (p->precision != HYDRO_FP64 && p->precision != HYDRO_FP32_BULK) return HYDRO_E_INVALID;
+  // FP32-bulk forms the weights d_k / (eps + beta_k)^2 in single precision:
+  // on flat data they reach 1 / eps^2, which must stay far below FLT_MAX
+  if (p->precision == HYDRO_FP32_BULK && !(p->weno_eps >= 1e-12)) return HYDRO_E_INVALID;
   if (p->rho_floor > 0.0 && !(p->p_floor > 0.0)) return HYDRO_E_INVALID;
   if (p->reconstruction != HYDRO_COMPONENTWISE && p->reconstruction != HYDRO_CHARACTERISTIC)
     return HYDRO_E_INVALID;

@@ -56,6 +56,7 @@ def test_strerror_names_every_code(lib):
     lambda p: setattr(p, "gamma", 1.0),
     lambda p: setattr(p, "weno_eps", 0.0),
     lambda p: setattr(p, "weno_eps", 1e-31),
+    lambda p: (setattr(p, "precision", hydro.FP32_BULK), setattr(p, "weno_eps", 1e-13)),
     lambda p: setattr(p, "reconstruction", 2),
     lambda p: (setattr(p, "reconstruction", hydro.CHARACTERISTIC), setattr(p, "precision", hydro.FP32_BULK)),
     lambda p: setattr(p, "cfl", -1.0),

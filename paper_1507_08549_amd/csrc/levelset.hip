@@ -41,12 +41,13 @@
 //                        minimum is taken over squared distances and rooted
 //                        once (the square root is monotone and correctly
 //                        rounded, so this equals the minimum of the roots).
-//                        Every corner starts from the point nearest to the tile
-//                        centre; a point whose distance to the tile's box, then
-//                        to the quarter's box, exceeds the largest current
-//                        minimum of that box's corners (with a relative margin
-//                        of 1e-9, far above rounding) is skipped: it cannot hold
-//                        the minimum of any of them.
+//                        Every corner starts from its distance to the point
+//                        nearest to the tile centre; a point whose distance to
+//                        the tile's box, then to the quarter's box, exceeds the
+//                        largest of those starting distances over the box's
+//                        corners (with a relative margin of 1e-9, far above
+//                        rounding) is skipped: it cannot hold the minimum of any
+//                        of them.
 #include "stage_kernel.hpp"
 
 namespace hy {
@@ -436,10 +437,10 @@ __global__ __launch_bounds__(LS_THREADS) void ls_distance_kernel(LsArgs a, const
     const double ex = x - px, ey = yv[r] - py;
     best[r] = ex * ex + ey * ey;
   }
-  // Bounds: every corner's minimum is at most its current best, so a point
-  // whose distance to a box exceeds the largest current best of the box's
-  // corners (with a relative margin of 1e-9, far above rounding) is nearest to
-  // none of them.
+  // Bounds: every corner's minimum is at most its starting distance, so a
+  // point whose distance to a box exceeds the largest starting distance of the
+  // box's corners (with a relative margin of 1e-9, far above rounding) is
+  // nearest to none of them.
   const double qb = wave_max_all(__builtin_fmax(on[0] ? best[0] : 0.0, on[1] ? best[1] : 0.0));
   if (lane == 0) ub[w] = qb;
   if (tid == 0) nkeep[0] = 0;

@@ -647,6 +647,20 @@ def levelset_leg(torch, hydro, inputs, n, steps, cpu):
         ct = time.perf_counter() - c0
         out["cpu_oracle"] = {"corner_updates_per_s": nc / ct, "cores": 1,
                              "sample": f"one advection step at full size, {ct:.2f} s"}
+        # one re-distancing of the current field on both sides: the oracle's
+        # brute force timed, the distances compared bit for bit
+        S_host = S.cpu().numpy()
+        dist = torch.zeros_like(S)
+        s.ls_redistance(S, dist)
+        c0 = time.perf_counter()
+        _, want_d, want_n = ls.redistance(S_host)
+        ct = time.perf_counter() - c0
+        out["cpu_oracle_redistance"] = {
+            "corners_per_s": nc / ct, "cores": 1, "front_points": want_n,
+            "sample": f"one re-distancing at full size (brute force), {ct:.2f} s",
+            "distances_bitwise_equal": bool(np.array_equal(dist.cpu().numpy(), want_d))}
+        log(f"levelset: oracle re-distancing {ct:.2f} s (GPU {out['redistance_us']:.1f} us), "
+            f"distances bitwise {out['cpu_oracle_redistance']['distances_bitwise_equal']}")
     s.close()
     return out
 

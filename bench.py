@@ -412,6 +412,28 @@ def adjoint_block(torch, hydro, inputs, args):
            "fd_rel_err_worst_component": int(comps[int(np.argmax(rel))]),
            "grad_rel_err_fp32_vs_fp64": float(np.linalg.norm(g32 - g64) / np.linalg.norm(g64)),
            "grad_rel_err_fp32_vs_fp64_max_component": float(np.max(np.abs(g32 - g64) / np.abs(g64)))}
+    if args.cpu_steps > 0:
+        # the plain-PyTorch reference adjoint (autograd through the textbook
+        # step, FP64, on the host) of one step at full size from the initial
+        # state, timed beside the GPU's and compared with it
+        from oracle import torch_ref
+        prm = inputs.kh_sine_params(n)
+        U0 = np.ascontiguousarray(inputs.kh_sine_state(a_np, prm), dtype=np.float64)
+        dt0, al0 = float(sched[0][0]), np.asarray(sched[1][0], dtype=np.float64)
+        lam = np.random.default_rng(11).standard_normal(U0.shape)
+        got = s64a.step_vjp(torch.tensor(U0, device="cuda"), dt0, al0,
+                            torch.tensor(lam, device="cuda")).cpu().numpy()
+        c0 = time.perf_counter()
+        want = torch_ref.vjp(prm, None, U0, dt0, [tuple(r) for r in al0], lam)
+        ct = time.perf_counter() - c0
+        adj["cpu_reference"] = {
+            "cell_step_vjps_per_s": n * n / ct, "cores": torch.get_num_threads(),
+            "kind": "plain PyTorch autograd, FP64",
+            "sample": f"one step's adjoint at full size from the initial state, {ct:.1f} s",
+            "rel_err_l2_gpu_vs_reference": float(np.linalg.norm(got - want) / np.linalg.norm(want))}
+        log(f"adjoint: reference step adjoint on the host {ct:.1f} s "
+            f"({adj['cpu_reference']['cores']} threads), GPU relative error "
+            f"{adj['cpu_reference']['rel_err_l2_gpu_vs_reference']:.1e}")
     log(f"adjoint: FP32 checkpointed ratio {adj['ratio']:.2f} (fwd {tf32c * 1e3:.1f} ms, bwd {tb32c * 1e3:.1f} ms); "
         f"FP64 checkpointed {adj['ratio_fp64_ckpt']:.2f}; all states {adj['ratio_fp64_all_states']:.2f} / "
         f"{adj['ratio_fp32_all_states']:.2f}; FD over {len(comps)} amplitudes: max rel err "

@@ -150,7 +150,7 @@ __device__ __forceinline__ Prim<R> adj_prim(const R U[4], R gm1, R& rinv) {
 template <typename R> struct JacPt { R u, v, H, hq; };  // hq = (gamma-1) |v|^2 / 2
 
 template <typename R>
-__device__ __forceinline__ JacPt<R> jac_point(R r, R mx, R my, R E, R gamma, R gm1) {
+__device__ __forceinline__ JacPt<R> jac_point(R r, R mx, R my, R E, R gm1) {
   const R U[4] = {r, mx, my, E};
   R rinv;
   const Prim<R> w = adj_prim(U, gm1, rinv);
@@ -369,7 +369,7 @@ __global__ __launch_bounds__(64 * NL) void vjp_line_kernel(VjpPass P) {
   const bool is_cell = L >= 3 && L < 3 + NA && k < na && line_ok;
   const bool own_lo = a0 == 0, own_hi = a0 <= na - 1 && na - 1 < a0 + NA;
   const bool is_ghost = !ring && line_ok && ((own_lo && k < 0) || (own_hi && k >= na && k < na + NG));
-  const JacPt<R> jc = jac_point<R>(cu[0], cu[1], cu[2], cu[3], gamma, gm1);
+  const JacPt<R> jc = jac_point<R>(cu[0], cu[1], cu[2], cu[3], gm1);
   R dU[4] = {R(0), R(0), R(0), R(0)};
 
 #pragma unroll

@@ -41,13 +41,13 @@
 //                        minimum is taken over squared distances and rooted
 //                        once (the square root is monotone and correctly
 //                        rounded, so this equals the minimum of the roots).
-//                        Every corner starts from its distance to the point
-//                        nearest to the tile centre; a point whose distance to
-//                        the tile's box, then to the quarter's box, exceeds the
-//                        largest of those starting distances over the box's
-//                        corners (with a relative margin of 1e-9, far above
-//                        rounding) is skipped: it cannot hold the minimum of any
-//                        of them.
+//                        Every corner starts from its distance to one point
+//                        near the tile centre (the nearest among every fourth
+//                        point); a point whose distance to the tile's box, then
+//                        to the quarter's box, exceeds the largest of those
+//                        starting distances over the box's corners (with a
+//                        relative margin of 1e-9, far above rounding) is
+//                        skipped: it cannot hold the minimum of any of them.
 #include "stage_kernel.hpp"
 
 namespace hy {
@@ -391,13 +391,14 @@ __global__ __launch_bounds__(LS_THREADS) void ls_distance_kernel(LsArgs a, const
   const double tx0 = a.xlo + (double)i0 * a.dx, tx1 = a.xlo + (double)i1 * a.dx;
   const double ty0 = a.ylo + (double)j0 * a.dy, ty1 = a.ylo + (double)j1 * a.dy;
 
-  // pass 1: the point nearest to the tile centre
+  // pass 1: the point nearest to the tile centre among every 4th point (any
+  // point bounds the corners' minima; a sample of the front is close enough)
   {
     const double cx = 0.5 * (tx0 + tx1), cy = 0.5 * (ty0 + ty1);
     double bc = __builtin_inf(), bx = 0.0, by = 0.0;
-    for (long long k = tid; k < np; k += 2 * LS_THREADS) {
+    for (long long k = (long long)tid * 4; k < np; k += 2 * 4 * LS_THREADS) {
       const double2 p0 = pp[k];
-      const double2 p1 = k + LS_THREADS < np ? pp[k + LS_THREADS] : p0;
+      const double2 p1 = k + 4 * LS_THREADS < np ? pp[k + 4 * LS_THREADS] : p0;
       const double ex = cx - p0.x, ey = cy - p0.y, fx = cx - p1.x, fy = cy - p1.y;
       const double d = ex * ex + ey * ey, e = fx * fx + fy * fy;
       if (d < bc) { bc = d; bx = p0.x; by = p0.y; }
@@ -433,7 +434,7 @@ __global__ __launch_bounds__(LS_THREADS) void ls_distance_kernel(LsArgs a, const
     const int j = qj0 + (lane / DQX) + 4 * r;
     yv[r] = a.ylo + (double)j * a.dy;
     on[r] = i < a.mx && j < a.my;
-    // the point nearest to the tile centre is a candidate of every corner
+    // the point found in pass 1 is a candidate of every corner
     const double ex = x - px, ey = yv[r] - py;
     best[r] = ex * ex + ey * ey;
   }

@@ -353,8 +353,10 @@ __global__ __launch_bounds__(LS_THREADS) void ls_front_kernel(LsArgs a, double* 
 // its own list.
 constexpr int DTX = 32, DTY = 16, DQX = 16, DQY = 8;
 constexpr int DW = LS_THREADS / 64;  // wavefronts per workgroup
-constexpr int DCH = 248;             // points per chunk (20 KB of LDS per workgroup)
-static_assert((DTX / DQX) * (DTY / DQY) == DW && DQX * DQY == 2 * 64 && DCH <= LS_THREADS,
+constexpr int DCH = 496;             // points per chunk
+constexpr int DPT = (DCH + LS_THREADS - 1) / LS_THREADS;  // a work item's points per chunk
+constexpr int QCAP = 128;            // a wavefront's list (16 KB of LDS per workgroup in all)
+static_assert((DTX / DQX) * (DTY / DQY) == DW && DQX * DQY == 2 * 64 && QCAP >= 64,
               "distance tile shape");
 
 // Max of a non-negative x over the wavefront, in every lane.
@@ -375,7 +377,7 @@ __device__ __forceinline__ double box_dist2(double qx, double qy, double x0, dou
 
 __global__ __launch_bounds__(LS_THREADS) void ls_distance_kernel(LsArgs a, const double* pts, double* dist) {
   __shared__ double P[2][DCH];      // the tile's candidates of a chunk
-  __shared__ double Q[DW][2][DCH];  // each wavefront's own candidates
+  __shared__ double Q[DW][2][QCAP];  // each wavefront's own candidates
   __shared__ double red[3][DW];     // pass 1: each wavefront's nearest point
   __shared__ double ub[DW];         // each quarter's bound
   __shared__ int nkeep[2];          // candidates of the chunk (alternating)
@@ -451,23 +453,49 @@ __global__ __launch_bounds__(LS_THREADS) void ls_distance_kernel(LsArgs a, const
   tb *= 1.0 + 1e-9;
   const double wb = qb * (1.0 + 1e-9);
 
-  double2 q = {0.0, 0.0};  // this work item's point of the chunk
-  if (tid < min(np, (long long)DCH)) q = pp[tid];
+  double2 q[DPT];  // this work item's points of the chunk
+#pragma unroll
+  for (int e = 0; e < DPT; ++e) {
+    const int k = tid + e * LS_THREADS;
+    q[e] = k < DCH && k < np ? pp[k] : double2{0.0, 0.0};
+  }
+  // a wavefront's list is run (and emptied) whenever another block of 64
+  // candidates might not fit
+  auto run_list = [&](int nq) {
+    __syncwarp();
+#pragma unroll 4
+    for (int k = 0; k < nq; ++k) {
+      const double ex = x - Q[w][0][k];
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const double ey = yv[r] - Q[w][1][k];
+        best[r] = __builtin_fmin(best[r], ex * ex + ey * ey);
+      }
+    }
+  };
   int c = 0;
   for (long long c0 = 0; c0 < np; c0 += DCH, c ^= 1) {
     const int m = (int)min((long long)DCH, np - c0);
-    if (tid < m && box_dist2(q.x, q.y, tx0, tx1, ty0, ty1) <= tb) {
-      const int at = atomicAdd(&nkeep[c], 1);
-      P[0][at] = q.x;
-      P[1][at] = q.y;
+#pragma unroll
+    for (int e = 0; e < DPT; ++e) {
+      const int k = tid + e * LS_THREADS;
+      if (k < m && box_dist2(q[e].x, q[e].y, tx0, tx1, ty0, ty1) <= tb) {
+        const int at = atomicAdd(&nkeep[c], 1);
+        P[0][at] = q[e].x;
+        P[1][at] = q[e].y;
+      }
+      if (k < DCH && c0 + DCH + k < np) q[e] = pp[c0 + DCH + k];  // next chunk, loaded during this one
     }
-    if (tid < DCH && c0 + DCH + tid < np) q = pp[c0 + DCH + tid];  // next chunk, loaded during this one
     __syncthreads();  // the chunk's candidates are complete
     const int nk = nkeep[c];
     if (tid == 0) nkeep[c ^ 1] = 0;  // last read in the previous chunk
     if (wave_on) {
       int nq = 0;
       for (int k0 = 0; k0 < nk; k0 += 64) {
+        if (nq > QCAP - 64) {
+          run_list(nq);
+          nq = 0;
+        }
         const int k = k0 + lane;
         double sx = 0.0, sy = 0.0;
         bool keep = false;
@@ -485,16 +513,7 @@ __global__ __launch_bounds__(LS_THREADS) void ls_distance_kernel(LsArgs a, const
         }
         nq += __popcll(bal);
       }
-      __syncwarp();
-#pragma unroll 4
-      for (int k = 0; k < nq; ++k) {
-        const double ex = x - Q[w][0][k];
-#pragma unroll
-        for (int r = 0; r < 2; ++r) {
-          const double ey = yv[r] - Q[w][1][k];
-          best[r] = __builtin_fmin(best[r], ex * ex + ey * ey);
-        }
-      }
+      run_list(nq);
     }
     __syncthreads();  // the chunk's candidates are consumed
   }
